@@ -1,0 +1,131 @@
+"""Oracle A: one time step of the scheme with relative velocities, as defined.
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+Follows section 1.2 of the paper step by step, in FP64, vectorised over nodes:
+
+1. conserved moments rho = sum_j f_j, q = sum_j v_j f_j, u = q / rho   eq. (rhoq)
+2. the relative velocity u~ (zero, alpha * u, or a given field)       section 1.2
+3. f^eq independent of u~ (second-order polynomial equilibrium,
+   reading S2 in the design doc)                                           section 1.2
+4. M(u~)_kj = P_k(v_j - u~) evaluated from the polynomials            eq. (MatMu)
+5. m = M(u~) f, m^eq = M(u~) f^eq                                     eq. (ftomu)
+6. m*_k = m_k + s_k (m^eq_k - m_k)                                    eq. (relaxationu)
+7. f* = M(u~)^{-1} m*  (LU solve with partial pivoting per node)      section 1.2
+8. f_j(x, t + dt) = f*_j(x - v_j dt, t), periodic                     eq. (transport)
+
+Arrays: populations ``f`` have shape (q, *grid) with grid = (Ny, Nx) in 2-D and
+(Nz, Ny, Nx) in 3-D (x fastest).  A u~ field has shape (d, *grid).  Lattice
+units: dx = 1, dt = dx / la.
+"""
+import numpy as np
+
+ZERO, FLUID, FIELD = 0, 1, 2
+
+
+def _flat(lat, a):
+    """(k, *grid) -> (N, k)."""
+    return a.reshape(a.shape[0], -1).T
+
+
+def conserved(lat, f, la=1.0):
+    """rho and u = q / rho at every node, eq. (rhoq).  u has shape (d, *grid)."""
+    v = lat.velocities(la)
+    rho = f.sum(axis=0)
+    q = np.stack([np.tensordot(v[:, a], f, axes=(0, 0)) for a in range(lat.d)])
+    return rho, q / rho
+
+
+def equilibrium(lat, rho, u, la=1.0):
+    """f^eq_j = w_j rho [1 + v.u/cs2 + (v.u)^2/(2 cs2^2) - |u|^2/(2 cs2)], cs2 = la^2/3.
+
+    The paper leaves f^eq open ("any general equilibrium", section 2); this is
+    reading S2.  u has shape (d, *grid); returns (q, *grid).
+    """
+    v = lat.velocities(la)
+    cs2 = la * la / 3.0
+    uu = sum(u[a] * u[a] for a in range(lat.d))
+    out = np.empty((lat.q,) + rho.shape)
+    for j in range(lat.q):
+        vu = sum(v[j, a] * u[a] for a in range(lat.d))
+        out[j] = lat.w[j] * rho * (1.0 + vu / cs2 + vu * vu / (2 * cs2 * cs2) - uu / (2 * cs2))
+    return out
+
+
+def moment_matrix(lat, ut, la=1.0):
+    """M(u~)_kj = P_k(v_j - u~), eq. (MatMu).
+
+    ut: array (N, d) of relative velocities (one row per node).  Returns (N, q, q).
+    """
+    v = lat.velocities(la)
+    n = ut.shape[0]
+    XYZ = []
+    for a in range(3):
+        if a < lat.d:
+            XYZ.append(v[None, :, a] - ut[:, a:a + 1])      # (N, q): component a of v_j - u~
+        else:
+            XYZ.append(np.zeros((n, lat.q)))
+    M = np.empty((n, lat.q, lat.q))
+    for k, P in enumerate(lat.basis):
+        M[:, k, :] = P(XYZ[0], XYZ[1], XYZ[2], la)
+    return M
+
+
+def relative_velocity(lat, u, mode, alpha=1.0, field=None):
+    """u~ per node: 0 (d'Humieres), alpha*u (alpha=1: cascaded), or a given field."""
+    if mode == ZERO:
+        return np.zeros_like(u)
+    if mode == FLUID:
+        return alpha * u
+    if mode == FIELD:
+        return np.asarray(field, dtype=np.float64)
+    raise ValueError(mode)
+
+
+def collide(lat, f, s, la=1.0, mode=ZERO, alpha=1.0, field=None):
+    """Relaxation phase of section 1.2 at every node; returns f* (q, *grid)."""
+    s = np.asarray(s, dtype=np.float64)
+    rho, u = conserved(lat, f, la)
+    ut = relative_velocity(lat, u, mode, alpha, field)
+    feq = equilibrium(lat, rho, u, la)
+    M = moment_matrix(lat, _flat(lat, ut), la)                  # (N, q, q)
+    m = np.einsum("nkj,nj->nk", M, _flat(lat, f))               # shifted moments
+    meq = np.einsum("nkj,nj->nk", M, _flat(lat, feq))           # shifted equilibrium moments
+    mstar = m + s[None, :] * (meq - m)
+    fstar = np.linalg.solve(M, mstar[:, :, None])[:, :, 0]      # M(u~)^{-1} m*
+    return fstar.T.reshape(f.shape)
+
+
+def stream(lat, fstar):
+    """Transport phase, eq. (transport): f_j(x) = f*_j(x - c_j), periodic."""
+    out = np.empty_like(fstar)
+    nd = fstar.ndim - 1
+    for j in range(lat.q):
+        shifts = [int(lat.c[j, a]) for a in range(lat.d)]
+        axes = [nd - 1 - a for a in range(lat.d)]                # x -> last axis
+        out[j] = np.roll(fstar[j], shift=shifts, axis=axes)
+    return out
+
+
+def step(lat, f, s, la=1.0, mode=ZERO, alpha=1.0, field=None):
+    """One full time step: relaxation then transport."""
+    return stream(lat, collide(lat, f, s, la, mode, alpha, field))
+
+
+def run(lat, f, s, nsteps, la=1.0, mode=ZERO, alpha=1.0, field=None):
+    for _ in range(nsteps):
+        f = step(lat, f, s, la, mode, alpha, field)
+    return f
+
+
+def fixed_moments(lat, f, la=1.0):
+    """m(0) = M(0) f at every node, shape (q, *grid)."""
+    M0 = moment_matrix(lat, np.zeros((1, lat.d)), la)[0]
+    return np.tensordot(M0, f, axes=(1, 0))
+
+
+def shift_matrix(lat, ut, la=1.0):
+    """T(u~) = M(u~) M(0)^{-1} (section 1.3), for a single u~ of length d."""
+    Mu = moment_matrix(lat, np.asarray(ut, dtype=np.float64)[None, :], la)[0]
+    M0 = moment_matrix(lat, np.zeros((1, lat.d)), la)[0]
+    return Mu @ np.linalg.inv(M0)

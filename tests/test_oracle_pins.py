@@ -1,0 +1,346 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a matrix or
+formula printed in the paper, a closed form, an exact invariant, a special case
+that reduces to a separately written scheme, or a physical law the paper
+derives (second-order equivalent equations).
+"""
+import os
+
+import numpy as np
+import pytest
+import sympy as sp
+
+from oracle import geier, lattices, mrt
+from oracle import scheme as A
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+S_GROUPED = [0, 0, 0, 1.4, 1.7, 1.7, 1.2, 1.2, 1.4]
+
+
+def far_from_eq(lat, shape, rng, amp=0.1, umax=0.1):
+    """Random state: f^eq(rho, u) times (1 + amp * U(-1, 1)) per population."""
+    rho = 1 + 0.05 * rng.standard_normal(shape)
+    u = umax * rng.uniform(-1, 1, (lat.d,) + shape)
+    feq = A.equilibrium(lat, rho, u)
+    return feq * (1 + amp * rng.uniform(-1, 1, feq.shape))
+
+
+def random_rates(lat, rng):
+    s = rng.uniform(0.6, 1.9, lat.q)
+    s[: lat.d + 1] = 0.0
+    return s
+
+
+# --------------------------------------------------------------------------
+# printed objects
+# --------------------------------------------------------------------------
+
+def test_M0_matches_printed_matort():
+    """eq. (matort): the oracle's D2Q9 polynomials and velocity order give the printed M(0)."""
+    rows = np.loadtxt(os.path.join(GOLDEN, "d2q9_M0_matort.txt"))
+    printed = rows[:, 1:]
+    for la in (1.0, 0.5, 3.0):
+        M0 = A.moment_matrix(lattices.make("d2q9"), np.zeros((1, 2)), la)[0]
+        expect = printed.copy()
+        expect[1:3] *= la                      # rows q_x, q_y carry lambda
+        assert np.array_equal(M0, expect), la
+
+
+def _appendix_a_blocks(u1, u2, la, d2_factor):
+    """Blocks A..D4 of Appendix A, typed from the paper; D2 scaled by d2_factor."""
+    n2 = u1 * u1 + u2 * u2
+    Ab = [[-u1], [-u2]]
+    B1 = [[3 / la ** 2 * n2], [(u1 ** 2 - u2 ** 2) / la ** 2], [u1 * u2 / la ** 2]]
+    B2 = [[-6 / la ** 2 * u1, -6 / la ** 2 * u2], [-2 / la ** 2 * u1, 2 / la ** 2 * u2],
+          [-u2 / la ** 2, -u1 / la ** 2]]
+    C1 = [[-3 / la ** 3 * u1 * (n2 + la ** 2)], [-3 / la ** 3 * u2 * (n2 + la ** 2)]]
+    C2 = [[3 / la ** 3 * (n2 + 2 * u1 ** 2), 6 / la ** 3 * u1 * u2],
+          [6 / la ** 3 * u1 * u2, 3 / la ** 3 * (n2 + 2 * u2 ** 2)]]
+    C3 = [[-2 / la * u1, -3 / la * u1, -6 / la * u2], [-2 / la * u2, 3 / la * u2, -6 / la * u1]]
+    D1 = [[9 / (2 * la ** 4) * (n2 ** 2 + 3 * la ** 2 * n2)]]
+    D2 = [[-d2_factor * 9 / (2 * la ** 4) * u1 * (la ** 2 + 2 * n2),
+           -d2_factor * 9 / (2 * la ** 4) * u2 * (la ** 2 + 2 * n2)]]
+    D3 = [[6 / la ** 2 * n2, 9 / la ** 2 * (u1 ** 2 - u2 ** 2), 36 / la ** 2 * u1 * u2]]
+    D4 = [[-6 / la * u1, -6 / la * u2]]
+    T = np.eye(9)
+    blocks = {(1, 0): Ab, (3, 0): B1, (3, 1): B2, (6, 0): C1, (6, 1): C2, (6, 3): C3,
+              (8, 0): D1, (8, 1): D2, (8, 3): D3, (8, 6): D4}
+    for (r, c), b in blocks.items():
+        b = np.array(b, dtype=np.float64)
+        T[r:r + b.shape[0], c:c + b.shape[1]] = b
+    return T
+
+
+@pytest.mark.parametrize("la", [1.0, 0.8, 2.0])
+def test_shift_matrix_matches_appendix_A(la):
+    """T(u~) = M(u~) M(0)^{-1} against the blocks of Appendix A (eq. (matTu)).
+
+    Every printed block matches except D2, which the paper prints with 9/2 where
+    the definition (and the paper's own Maple procedure) gives 9 (reading S6).
+    """
+    lat = lattices.make("d2q9")
+    rng = np.random.default_rng(7)
+    for _ in range(5):
+        u = rng.uniform(-0.4, 0.4, 2) * la
+        T = A.shift_matrix(lat, u, la)
+        assert np.allclose(T, _appendix_a_blocks(u[0], u[1], la, 2.0), atol=1e-13, rtol=0)
+        printed = _appendix_a_blocks(u[0], u[1], la, 1.0)
+        diff = np.abs(T - printed) > 1e-9
+        assert diff.sum() == 2 and diff[8, 1] and diff[8, 2]   # only the two D2 entries
+
+
+def _symbolic_T(lat):
+    """Rebuild of the Appendix A Maple procedure in sympy, on the oracle's own basis."""
+    la = sp.Symbol("la", positive=True)
+    ux, uy, uz = sp.symbols("ux uy uz")
+    U = [ux, uy, uz][: lat.d]
+    V = [[la * int(c) for c in row] for row in lat.c]
+    zero3 = [0, 0, 0]
+
+    def M(u):
+        uu = list(u) + [0] * (3 - len(u))
+        return sp.Matrix(lat.q, lat.q, lambda k, j: sp.expand(lat.basis[k](
+            V[j][0] - uu[0], V[j][1] - uu[1], V[j][2] - uu[2], la)))
+
+    M0 = M(zero3[: lat.d])
+    T = (M(U) * M0.inv()).applyfunc(sp.simplify)
+    return T, U, la
+
+
+def test_shift_symbolic_d2q9_paper():
+    """Symbolic: T(0) = I, block unit-lower-triangular, and Proposition th:csd2q9."""
+    lat = lattices.make("d2q9")
+    T, U, la = _symbolic_T(lat)
+    assert T.subs({U[0]: 0, U[1]: 0}) == sp.eye(9)
+    for k in range(9):
+        assert T[k, k] == 1
+        for l in range(k + 1, 9):
+            assert T[k, l] == 0
+    vx, vy = sp.symbols("vx vy")
+    Tv = T.subs({U[0]: vx, U[1]: vy}, simultaneous=True)
+    Tsum = T.subs({U[0]: U[0] + vx, U[1]: U[1] + vy}, simultaneous=True)
+    assert (Tsum - T * Tv).applyfunc(sp.expand) == sp.zeros(9, 9)
+    assert (T * Tv - Tv * T).applyfunc(sp.expand) == sp.zeros(9, 9)
+
+
+@pytest.mark.parametrize("name", lattices.ALL)
+def test_shift_structure_numeric(name):
+    """All four bases: rank q, T(0) = I, unit lower-triangular, morphism (numerically)."""
+    lat = lattices.make(name)
+    rng = np.random.default_rng(3)
+    M0 = A.moment_matrix(lat, np.zeros((1, lat.d)))[0]
+    assert np.linalg.matrix_rank(M0) == lat.q
+    assert np.allclose(A.shift_matrix(lat, np.zeros(lat.d)), np.eye(lat.q), atol=1e-14)
+    for _ in range(4):
+        u, v = rng.uniform(-0.4, 0.4, (2, lat.d))
+        Tu, Tv = A.shift_matrix(lat, u), A.shift_matrix(lat, v)
+        assert np.allclose(np.triu(Tu, 1), 0, atol=1e-13)
+        assert np.allclose(np.diag(Tu), 1, atol=1e-13)
+        assert np.allclose(A.shift_matrix(lat, u + v), Tu @ Tv, atol=1e-12)
+        assert np.allclose(Tu @ Tv, Tv @ Tu, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# equilibrium (reading S2)
+# --------------------------------------------------------------------------
+
+def test_equilibrium_moments_d2q9_closed_form():
+    """Paper-basis moments of f^eq are the standard Lallemand-Luo equilibria (la = 1)."""
+    lat = lattices.make("d2q9")
+    rng = np.random.default_rng(11)
+    rho = 1 + 0.1 * rng.standard_normal(20)
+    u = 0.2 * rng.uniform(-1, 1, (2, 20))
+    jx, jy = rho * u[0], rho * u[1]
+    m = A.fixed_moments(lat, A.equilibrium(lat, rho, u))
+    j2 = (jx * jx + jy * jy) / rho
+    expect = [rho, jx, jy, -2 * rho + 3 * j2, (jx * jx - jy * jy) / rho, jx * jy / rho, -jx, -jy, rho - 3 * j2]
+    for k in range(9):
+        assert np.allclose(m[k], expect[k], atol=1e-14), k
+
+
+@pytest.mark.parametrize("name", ["d2q9", "d3q19", "d3q27"])
+def test_equilibrium_hydrodynamic_moments(name):
+    """f^eq reproduces rho, rho u and the Euler flux rho u u + rho cs2 I (Def. th:defmflux)."""
+    lat = lattices.make(name)
+    rng = np.random.default_rng(5)
+    for la in (1.0, 1.7):
+        rho = 1 + 0.1 * rng.standard_normal(10)
+        u = 0.2 * la * rng.uniform(-1, 1, (lat.d, 10))
+        feq = A.equilibrium(lat, rho, u, la)
+        v = lat.velocities(la)
+        assert np.allclose(feq.sum(0), rho, atol=1e-14)
+        for a in range(lat.d):
+            assert np.allclose(np.tensordot(v[:, a], feq, 1), rho * u[a], atol=1e-14)
+            for b in range(lat.d):
+                F = np.tensordot(v[:, a] * v[:, b], feq, 1)
+                assert np.allclose(F, rho * u[a] * u[b] + (a == b) * rho * la * la / 3, atol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# collision invariants and special cases
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", lattices.ALL)
+@pytest.mark.parametrize("mode", [A.ZERO, A.FLUID, A.FIELD])
+def test_collision_conserves_mass_momentum(name, mode):
+    """s_k = 0 on the conserved moments (section 1.1) => rho, q unchanged by the relaxation."""
+    lat = lattices.make(name)
+    rng = np.random.default_rng(1)
+    shape = (4, 5) if lat.d == 2 else (3, 4, 5)
+    f = far_from_eq(lat, shape, rng)
+    field = rng.uniform(-0.3, 0.3, (lat.d,) + shape)
+    fs = A.collide(lat, f, random_rates(lat, rng), 1.0, mode, 0.7, field)
+    scale = np.abs(f).sum(0)
+    assert np.all(np.abs(fs.sum(0) - f.sum(0)) <= 8e-16 * scale * lat.q)
+    for a in range(lat.d):
+        d = np.tensordot(lat.c[:, a].astype(float), fs - f, 1)
+        assert np.all(np.abs(d) <= 8e-16 * scale * lat.q)
+
+
+@pytest.mark.parametrize("name", lattices.ALL)
+def test_equal_rates_reduce_to_bgk_for_any_ut(name):
+    """Equal non-conserved rates: f* = f + s (f^eq - f) whatever u~ (T lower-triangular)."""
+    lat = lattices.make(name)
+    rng = np.random.default_rng(2)
+    shape = (3, 4) if lat.d == 2 else (2, 3, 4)
+    f = far_from_eq(lat, shape, rng)
+    s = np.full(lat.q, 1.3)
+    s[: lat.d + 1] = 0
+    rho, u = A.conserved(lat, f)
+    bgk = f + 1.3 * (A.equilibrium(lat, rho, u) - f)
+    field = rng.uniform(-0.3, 0.3, (lat.d,) + shape)
+    for mode in (A.ZERO, A.FLUID, A.FIELD):
+        fs = A.collide(lat, f, s, 1.0, mode, 1.0, field)
+        assert np.allclose(fs, bgk, atol=2e-15, rtol=0)
+
+
+def test_zero_relative_velocity_is_dhumieres_mrt():
+    """u~ = 0 reproduces the separately written d'Humieres step (section 1.2)."""
+    lat = lattices.make("d2q9")
+    rng = np.random.default_rng(4)
+    f = far_from_eq(lat, (6, 7), rng)
+    for la in (1.0, 1.3):
+        a = A.step(lat, f, S_GROUPED, la, A.ZERO)
+        b = mrt.mrt_step(f, S_GROUPED, la)
+        assert np.abs(a - b).max() <= 1e-15
+
+
+def test_geier_C_structure():
+    """C(u) = M_g(u) tM(0) is lower triangular except the 2x2 block on (3, 4) (Appendix B)."""
+    C = geier.upper_structure(np.array([0.13, -0.21]))
+    upper = np.triu(C, 1)
+    upper[3, 4] = 0
+    assert np.abs(upper).max() <= 1e-14
+    assert abs(C[3, 4]) > 0
+
+
+@pytest.mark.parametrize("la", [1.0, 0.6])
+def test_fluid_relative_velocity_with_geier_basis_is_cascaded(la):
+    """Proposition th:cascd2q9: Geier basis + u~ = u equals the Appendix B g-vector scheme."""
+    lat = lattices.make("d2q9_geier")
+    rng = np.random.default_rng(6)
+    f = far_from_eq(lat, (5, 6), rng, umax=0.2)
+    s = [0, 0, 0, 1.1, 1.8, 1.6, 1.25, 1.35, 1.5]
+    a = A.step(lat, f, s, la, A.FLUID, 1.0)
+    b = geier.geier_step(f, s, la)
+    assert np.abs(a - b).max() <= 1e-13
+    # and differs from the fixed-frame scheme at this distance from equilibrium
+    c = A.step(lat, f, s, la, A.ZERO)
+    assert np.abs(a - c).max() > 1e-4
+
+
+@pytest.mark.parametrize("name", lattices.ALL)
+def test_lambda_scaling(name):
+    """The step at scale la with u~ equals the step at la = 1 with u~/la (acoustic scaling)."""
+    lat = lattices.make(name)
+    rng = np.random.default_rng(8)
+    shape = (3, 4) if lat.d == 2 else (2, 3, 4)
+    f = far_from_eq(lat, shape, rng)
+    s = random_rates(lat, rng)
+    la = 1.9
+    field = rng.uniform(-0.3, 0.3, (lat.d,) + shape)
+    a = A.collide(lat, f, s, la, A.FIELD, field=la * field)
+    b = A.collide(lat, f, s, 1.0, A.FIELD, field=field)
+    assert np.allclose(a, b, atol=2e-14, rtol=0)
+
+
+# --------------------------------------------------------------------------
+# transport
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["d2q9", "d3q19", "d3q27"])
+def test_stream_moves_each_population_along_its_velocity(name):
+    """eq. (transport): a unit at node x0 in population j arrives at x0 + c_j (periodic)."""
+    lat = lattices.make(name)
+    shape = (5, 7) if lat.d == 2 else (4, 5, 7)
+    f = np.zeros((lat.q,) + shape)
+    x0 = (4, 6) if lat.d == 2 else (3, 4, 6)          # (y, x) / (z, y, x): at the upper edges
+    for j in range(lat.q):
+        f[(j,) + x0] = 1.0
+    g = A.stream(lat, f)
+    for j in range(lat.q):
+        c = lat.c[j][: lat.d][::-1]                    # (cy, cx) / (cz, cy, cx)
+        dst = tuple((x0[i] + c[i]) % shape[i] for i in range(lat.d))
+        assert g[(j,) + dst] == 1.0 and g[j].sum() == 1.0
+
+
+@pytest.mark.parametrize("name", ["d2q9", "d3q19"])
+def test_stream_period_is_identity_bitwise(name):
+    lat = lattices.make(name)
+    rng = np.random.default_rng(9)
+    L = 6
+    shape = (L, L) if lat.d == 2 else (L, L, L)
+    f = rng.standard_normal((lat.q,) + shape)
+    g = f
+    for _ in range(L):
+        g = A.stream(lat, g)
+    assert np.array_equal(g, f)
+
+
+# --------------------------------------------------------------------------
+# second-order physics: shear-wave viscosity (Prop. th:ordre2, Cor. th:coreqo2)
+# --------------------------------------------------------------------------
+
+def _shear_decay_rate(lat, s, mode, L=32, steps=300, U=1e-3, la=1.0):
+    """Fit the decay of u_x = U sin(2 pi y / L) and return the measured viscosity."""
+    shape = (L, L) if lat.d == 2 else (4, L, 4)
+    y = np.arange(L)
+    prof = U * np.sin(2 * np.pi * y / L)
+    u = np.zeros((lat.d,) + shape)
+    if lat.d == 2:
+        u[0] = prof[:, None]
+    else:
+        u[0] = prof[None, :, None]
+    f = A.equilibrium(lat, np.ones(shape), u, la)
+    amps, ts = [], []
+    for t in range(steps + 1):
+        if t >= 50 and t % 25 == 0:
+            _, uu = A.conserved(lat, f, la)
+            ux = uu[0].mean(axis=-1) if lat.d == 2 else uu[0].mean(axis=(0, 2))
+            amps.append(2 / L * np.sum(ux * np.sin(2 * np.pi * y / L)))
+            ts.append(t)
+        f = A.step(lat, f, s, la, mode)
+    k = 2 * np.pi / L
+    slope = np.polyfit(ts, np.log(amps), 1)[0]
+    return -slope / (k * k)
+
+
+@pytest.mark.parametrize("name,mode", [("d2q9", A.ZERO), ("d2q9", A.FLUID),
+                                       ("d2q9_geier", A.FLUID), ("d3q19", A.ZERO),
+                                       ("d3q19", A.FLUID), ("d3q27", A.FLUID)])
+def test_shear_wave_viscosity(name, mode):
+    """nu = (la dx / 3)(1/s - 1/2) for u~ = 0 and u~ = u alike (section 2, Cor. th:coreqo2)."""
+    lat = lattices.make(name)
+    s_nu = 1.7
+    if name == "d2q9":
+        s = [0, 0, 0, 1.4, s_nu, s_nu, 1.2, 1.2, 1.4]
+    elif name == "d2q9_geier":
+        s = [0, 0, 0, 1.4, s_nu, s_nu, 1.2, 1.2, 1.4]
+    else:
+        s = [0.0] * 4 + [1.1] + [s_nu] * 5 + [1.5] * 6 + ([1.5] if lat.q == 27 else []) \
+            + [1.8] * (lat.q - 16 - (1 if lat.q == 27 else 0))
+    assert len(s) == lat.q
+    nu = _shear_decay_rate(lat, s, mode, L=32, steps=300)
+    nu_th = (1 / s_nu - 0.5) / 3
+    assert abs(nu / nu_th - 1) < 5e-3, (nu, nu_th)

@@ -1,0 +1,190 @@
+"""Throughput of the relative-velocity lattice Boltzmann step on one MI355X.
+
+Default workload: D3Q19, 256^3 periodic, FP32 populations, Taylor-Green vortex
+(U0 = 0.05) plus 1e-5 seeded noise, u~ = local fluid velocity (cascaded choice),
+rates bulk 1.1 / shear 1.95 / third order 1.5 / fourth order 1.8.
+
+A "step" is one full time step of the scheme (relaxation in the moving frame,
+then transport) over every node.  K steps are timed as one lbmrv_step call on
+the current stream, bracketed by a device synchronisation; inputs are resident
+in HBM before the timed region.  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS + % of HBM roofline (D3Q19 FP32 256³); adjoint cost ratio vs fwd"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (lattice, dims, storage, mode, alpha, builder)
+    "d3q19_tgv256_f32_fluid": ("d3q19", (256, 256, 256), "f32", "fluid"),
+    "d3q19_tgv256_f16dev_fluid": ("d3q19", (256, 256, 256), "f16dev", "fluid"),
+    "d3q27_tgv192_f32_field": ("d3q27", (192, 192, 192), "f32", "field"),
+    "d2q9_shear2048_f32_fluid": ("d2q9", (2048, 2048), "f32", "fluid"),
+    "d2q9_shear4096_f32_fluid": ("d2q9", (4096, 4096), "f32", "fluid"),
+}
+
+
+def build_state(name, ctx, torch):
+    """Seeded initial populations in HBM (built by the library from rho, u, noise)."""
+    from paper_1312_3297_amd import workloads as W
+    lattice, dims, storage, mode = WORKLOADS[name]
+    if lattice == "d3q19":
+        rho, u = W.taylor_green(dims[0], 0.05)
+        noise, amp, seed = True, 1e-5, 1313
+    elif lattice == "d3q27":
+        rho, u = W.taylor_green(dims[0], 0.05)
+        noise, amp, seed = True, 1e-5, 1314
+    else:
+        rho, u = W.double_shear_layer(dims[0])
+        noise, amp, seed = False, 0.0, 0
+    d_rho = torch.from_numpy(rho).to("cuda")
+    d_u = torch.from_numpy(u).to("cuda")
+    d_noise = torch.from_numpy(W.noise(ctx.q, rho.shape, seed)).to("cuda") if noise else None
+    f = ctx.init_equilibrium(d_rho, d_u, d_noise, amp)
+    field = None
+    if mode == "field":
+        # prescribed relative velocity: half the initial fluid velocity, frozen
+        field = (0.5 * d_u).to(torch.float32).contiguous()
+    del d_rho, d_noise
+    torch.cuda.synchronize()
+    return f, field
+
+
+def rates_for(lattice):
+    from paper_1312_3297_amd import workloads as W
+    return {"d2q9": W.RATES_D2Q9_SHEAR_LAYER, "d3q19": W.RATES_D3Q19, "d3q27": W.RATES_D3Q27}[lattice]
+
+
+def cpu_baseline(name, budget_s=15.0):
+    """The FP64 oracle (NumPy, one thread) on a bounded sample of the workload:
+    a sub-block of the same initial state, stepped for about budget_s seconds."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:  # pragma: no cover
+        threadpool_limits = None
+    from oracle import lattices, scheme
+    from paper_1312_3297_amd import workloads as W
+    lattice, dims, storage, mode = WORKLOADS[name]
+    lat = lattices.make({"d2q9": "d2q9_paper"}.get(lattice, lattice))
+    if lat.d == 3:
+        sub = (16, 32, 32)
+        rho, u = W.taylor_green(dims[0], 0.05, shape=sub)
+    else:
+        sub = (64, 128)
+        rho, u = W.double_shear_layer(dims[0])
+        rho, u = rho[: sub[0], : sub[1]], u[:, : sub[0], : sub[1]]
+    f = scheme.equilibrium(lat, rho, u)
+    s = rates_for(lattice)
+    smode = {"zero": scheme.ZERO, "fluid": scheme.FLUID, "field": scheme.FIELD}[mode]
+    field = 0.5 * u if mode == "field" else None
+    import contextlib
+    with (threadpool_limits(1) if threadpool_limits else contextlib.nullcontext()):
+        t0 = time.perf_counter()
+        steps = 0
+        while True:
+            f = scheme.step(lat, f, s, 1.0, smode, 1.0, field)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el >= budget_s:
+                break
+    nodes = int(np.prod(sub))
+    return {"value": nodes * steps / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": "Oracle A (NumPy FP64, per-node LU) on a %s sub-block of the same initial state, %d steps "
+                      "in %.1f s" % ("x".join(str(x) for x in reversed(sub)), steps, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="d3q19_tgv256_f32_fluid", choices=sorted(WORKLOADS))
+    ap.add_argument("--streaming", default="pull", choices=["pull", "push"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--traffic-gb", type=float, default=None,
+                    help="HBM bytes per launch of the dominant kernel from rocprofv3 counters (GB)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(domain decomposition is described in DESIGN.md, not implemented)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1312_3297_amd.lbmrv import Lbmrv
+
+    name = args.workload
+    lattice, dims, storage, mode = WORKLOADS[name]
+    ctx = Lbmrv(lattice, rates_for(lattice), dims, storage)
+    ctx.set_streaming(args.streaming)
+    f, field = build_state(name, ctx, torch)
+    g = torch.empty_like(f)
+    stream = torch.cuda.current_stream()
+
+    # warmup
+    ctx.step(f, g, mode, 1.0, field, args.warmup)
+    f, g = g, f
+    torch.cuda.synchronize()
+
+    K = args.steps
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    ctx.step(f, g, mode, 1.0, field, K)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    f, g = g, f
+
+    mass, mom, finite = ctx.conservation(f)
+    N = ctx.N
+    q = ctx.q
+    b = {"f64": 8, "f32": 4, "f32dev": 4, "f16dev": 2}[storage]
+    # kernel launches inside the call: pull = collide + (K-1) fused + transport;
+    # push = K fused (+ one split step when K is even).  Every launch reads and
+    # writes q populations per node.
+    launches = K + 1 if args.streaming == "pull" else (K if K % 2 else K + 1)
+    bytes_per_launch = 2 * q * b * N + (ctx.d * 4 * N if mode == "field" else 0)
+    avg_launch_s = ms * 1e-3 / launches
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    mlups = N * K / (ms * 1e-3) / 1e6
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32", "f32dev": "f32", "f16dev": "f16-storage/f32"}[storage],
+        "data": "synthetic",
+        "config": {"workload": name, "lattice": lattice, "grid": list(dims), "storage": storage,
+                   "relative_velocity": mode, "streaming": args.streaming, "nodes": N},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": args.traffic_gb},
+        "state_finite": bool(finite),
+        "wall_s": round(wall, 4),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(name, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

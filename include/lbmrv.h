@@ -1,0 +1,194 @@
+/*
+ * lbmrv: lattice Boltzmann schemes with relative velocities on AMD MI355X (gfx950).
+ *
+ * C ABI of the HIP library liblbmrv.so.  Plain pointers and sizes only.
+ *
+ * The scheme (Dubois, Fevrier, Graille, "Lattice Boltzmann schemes with relative
+ * velocities", section 1): at every node the populations f are mapped to the
+ * moments of a polynomial basis P_k evaluated at v_j - u~ (eq. (MatMu)), relaxed
+ * diagonally towards equilibrium in that moving frame (eq. (relaxationu)),
+ * mapped back and transported along the lattice velocities (eq. (transport)).
+ * u~ = 0 is the d'Humieres MRT scheme; u~ = u = q / rho with the Geier basis is
+ * the cascaded scheme (Prop. th:cascd2q9).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Lattice units.  The node spacing is dx = 1 and the velocities are
+ * v_j = lambda c_j with integer directions c_j (eq. (lambda): dt = dx / lambda).
+ * Velocities passed in or returned (u, u~) are in the same units as v_j.
+ *
+ * Direction order (the index j of the population arrays):
+ *   D2Q9  (section 1.3): (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1)
+ *   D3Q19: (0,0,0); (1,0,0) (-1,0,0) (0,1,0) (0,-1,0) (0,0,1) (0,0,-1);
+ *          (1,1,0) (-1,-1,0) (1,-1,0) (-1,1,0) (1,0,1) (-1,0,-1) (1,0,-1) (-1,0,1)
+ *          (0,1,1) (0,-1,-1) (0,1,-1) (0,-1,1)
+ *   D3Q27: the 19 above, then (1,1,1) (-1,-1,-1) (1,1,-1) (-1,-1,1) (1,-1,1)
+ *          (-1,1,-1) (-1,1,1) (1,-1,-1)
+ *
+ * Moment bases (index k of the rates s_k):
+ *   LBMRV_BASIS_DEFAULT, D2Q9: eq. (mom) of the paper, in its order
+ *     1, X, Y, (3|X|^2-4l^2)/l^2, (X^2-Y^2)/l^2, XY/l^2, X(3|X|^2-5l^2)/l^3,
+ *     Y(3|X|^2-5l^2)/l^3, (9/2|X|^4 - 21/2 l^2|X|^2 + 4 l^4)/l^4
+ *   LBMRV_BASIS_GEIER, D2Q9: eq. (polgeier): 1, X, Y, X^2+Y^2, X^2-Y^2, XY, XY^2, X^2Y, X^2Y^2
+ *   LBMRV_BASIS_DEFAULT, D3Q19: 1; X, Y, Z; |X|^2, 2X^2-Y^2-Z^2, Y^2-Z^2, XY, YZ, XZ;
+ *     XY^2, XZ^2, X^2Y, YZ^2, X^2Z, Y^2Z; X^2Y^2, X^2Z^2, Y^2Z^2
+ *   LBMRV_BASIS_DEFAULT, D3Q27: the D3Q19 list with XYZ inserted after Y^2Z, then
+ *     X^2Y^2, X^2Z^2, Y^2Z^2, X^2YZ, XY^2Z, XYZ^2, X^2Y^2Z, X^2YZ^2, XY^2Z^2, X^2Y^2Z^2
+ *   Equilibrium: f^eq_j = w_j rho (1 + v_j.u/cs2 + (v_j.u)^2/(2 cs2^2) - |u|^2/(2 cs2)),
+ *   cs2 = lambda^2/3, standard weights; independent of u~ (section 1.2).
+ *
+ * Population arrays are structure-of-arrays: element (j, x, y, z) sits at
+ *   f[j * N + (z * ny + y) * nx + x],   N = nx * ny * nz  (nz = 1 in 2-D),
+ * with element type by storage:
+ *   LBMRV_F64     double, f itself
+ *   LBMRV_F32     float,  f itself
+ *   LBMRV_F32DEV  float,  the deviation f_j - w_j rho0
+ *   LBMRV_F16DEV  IEEE binary16, the deviation f_j - w_j rho0 (rounded to
+ *                 nearest-even on store, subnormals kept); arithmetic in FP32
+ * Arithmetic is FP64 for LBMRV_F64 and FP32 otherwise.  Every axis is periodic.
+ *
+ * Memory and streams.  All arrays passed to lbmrv_step / lbmrv_moments /
+ * lbmrv_conservation are device pointers owned by the caller, aligned to their
+ * element size, on the device that is current when the call is made.  A
+ * `hip_stream` argument is a hipStream_t (NULL = the null stream); work is
+ * enqueued on it asynchronously unless stated otherwise.  The context owns only
+ * its parameters and (after the first lbmrv_conservation call) a small device
+ * buffer for partial sums.
+ *
+ * Errors.  Every int-returning call returns LBMRV_OK (0) or a negative code.
+ * Arguments are validated on the host before any HIP call, so an invalid call
+ * has no device-side effect.  lbmrv_strerror gives a message.
+ */
+#ifndef LBMRV_H
+#define LBMRV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBMRV_OK 0
+#define LBMRV_ERR_INVALID_ARG (-1)   /* a pointer, size, enum or rate is invalid    */
+#define LBMRV_ERR_UNSUPPORTED (-2)   /* valid request that this build cannot serve  */
+#define LBMRV_ERR_HIP (-4)           /* a HIP runtime call failed                   */
+#define LBMRV_ERR_NONFINITE (-5)     /* lbmrv_conservation found a NaN or infinity  */
+#define LBMRV_ERR_ALIGNMENT (-6)     /* a pointer is not aligned to its element     */
+
+enum lbmrv_lattice { LBMRV_D2Q9 = 0, LBMRV_D3Q19 = 1, LBMRV_D3Q27 = 2 };
+enum lbmrv_basis { LBMRV_BASIS_DEFAULT = 0, LBMRV_BASIS_GEIER = 1 };
+enum lbmrv_storage { LBMRV_F64 = 0, LBMRV_F32 = 1, LBMRV_F32DEV = 2, LBMRV_F16DEV = 3 };
+enum lbmrv_utmode { LBMRV_UT_ZERO = 0, LBMRV_UT_FLUID = 1, LBMRV_UT_FIELD = 2 };
+enum lbmrv_streaming { LBMRV_STREAM_PULL = 0, LBMRV_STREAM_PUSH = 1 };
+
+typedef struct lbmrv_ctx lbmrv_ctx;
+
+/*
+ * Create a context for one lattice, basis, scale, rate vector, grid and storage.
+ *   out      receives the context (set to NULL on error)
+ *   lattice  enum lbmrv_lattice
+ *   basis    enum lbmrv_basis (GEIER only with D2Q9)
+ *   lambda   velocity scale of eq. (lambda), finite and > 0
+ *   s        q relaxation rates, one per basis element in the order above;
+ *            s_k for the conserved moments (k = 0..d) must be exactly 0
+ *            (section 1.1), the others in [0, 2]
+ *   dims     d extents (nx, ny[, nz]), each >= 1, q*nx*ny*nz < 2^32
+ *   storage  enum lbmrv_storage
+ *   rho0     reference density of the deviation storages (finite; ignored
+ *            for LBMRV_F64 and LBMRV_F32)
+ * Makes no HIP call.  Errors: INVALID_ARG.
+ */
+int lbmrv_create(lbmrv_ctx **out, int lattice, int basis, double lambda, const double *s,
+                 const int64_t *dims, int storage, double rho0);
+
+/* Replace the q relaxation rates (same rules as lbmrv_create).  No HIP call. */
+int lbmrv_set_rates(lbmrv_ctx *c, const double *s);
+
+/*
+ * Select the streaming form used by lbmrv_step: LBMRV_STREAM_PULL (default:
+ * each node gathers f*_j(x - c_j), the array holds post-collision values between
+ * fused steps) or LBMRV_STREAM_PUSH (each node scatters to x + c_j, the array
+ * holds pre-collision values).  Both give the same f(t + n dt).  No HIP call.
+ */
+int lbmrv_set_streaming(lbmrv_ctx *c, int kind);
+
+/* Query: q, d, N (nodes), bytes per stored population. */
+int lbmrv_info(const lbmrv_ctx *c, int64_t *q, int64_t *d, int64_t *nodes, int64_t *bytes_per_pop);
+
+/*
+ * Advance nsteps full time steps (relaxation then transport, section 1.2):
+ * f_out <- f(t + nsteps dt) given f_in = f(t), both pre-collision.
+ *   f_in, f_out  distinct device arrays of q*N elements of the storage type.
+ *                f_in is the ping-pong partner and is overwritten (its
+ *                contents are unspecified on return when nsteps >= 1).
+ *                nsteps = 0 copies f_in to f_out.
+ *   ut_mode      LBMRV_UT_ZERO (u~ = 0), LBMRV_UT_FLUID (u~ = ut_alpha * u at
+ *                every node and step; ut_alpha = 1 is the cascaded choice) or
+ *                LBMRV_UT_FIELD (u~(x) read from ut_field, fixed over the call)
+ *   ut_alpha     finite
+ *   ut_field     FIELD mode: device float array [d][N] (SoA, same node order),
+ *                otherwise ignored (may be NULL)
+ *   nsteps       >= 0
+ * Errors: INVALID_ARG, ALIGNMENT, HIP.
+ */
+int lbmrv_step(lbmrv_ctx *c, void *f_in, void *f_out, int ut_mode, double ut_alpha,
+               const float *ut_field, int64_t nsteps, void *hip_stream);
+
+/*
+ * The two half-steps of section 1.2 on their own, for checks of non-conserved
+ * moments and for external drivers:
+ *   lbmrv_collide:  f_out(x) <- f*(x), the relaxation at every node (f_out may
+ *                   equal f_in: the update is node-local)
+ *   lbmrv_transport: f_out_j(x) <- f_in_j(x - c_j) (eq. (transport)); f_out != f_in
+ */
+int lbmrv_collide(lbmrv_ctx *c, const void *f_in, void *f_out, int ut_mode, double ut_alpha,
+                  const float *ut_field, void *hip_stream);
+int lbmrv_transport(lbmrv_ctx *c, const void *f_in, void *f_out, void *hip_stream);
+
+/*
+ * Per-node macroscopic fields of f (eq. (rhoq)):
+ *   rho  [N], u [d][N] (u = q / rho, physical units), and, if m0 is not NULL,
+ *   m0 [q][N] = M(0) f, the fixed-frame moments of the user basis.
+ * Output element type: double for LBMRV_F64, float otherwise.  Errors: as step.
+ */
+int lbmrv_moments(lbmrv_ctx *c, const void *f, void *rho, void *u, void *m0, void *hip_stream);
+
+/*
+ * Global sums in FP64: out[0] = sum_x rho, out[1 .. d] = sum_x q^alpha
+ * (physical units), out[d+1 .. 3] = 0.  Synchronises hip_stream.  Returns
+ * LBMRV_ERR_NONFINITE (with out filled) if any population is NaN or infinite.
+ */
+int lbmrv_conservation(lbmrv_ctx *c, const void *f, double out[4], void *hip_stream);
+
+/*
+ * Initial state (K5): f_out <- f^eq(rho, u) + noise_amp * noise, computed in
+ * FP64 and stored in the context's storage type (minus w_j rho0 for the
+ * deviation storages, rounded to nearest-even).
+ *   rho [N], u [d][N] (physical units), noise [q][N] or NULL: device doubles.
+ */
+int lbmrv_init_equilibrium(lbmrv_ctx *c, const double *rho, const double *u, const double *noise,
+                           double noise_amp, void *f_out, void *hip_stream);
+
+/*
+ * Storage conversion.  lbmrv_import: out <- rn(f - w_j rho0) in the storage
+ * type from FP64 populations f [q][N]; lbmrv_export: f <- in + w_j rho0 in FP64.
+ * Device arrays.  For LBMRV_F64 both are copies.
+ */
+int lbmrv_import(lbmrv_ctx *c, const double *f, void *out, void *hip_stream);
+int lbmrv_export(lbmrv_ctx *c, const void *in, double *f, void *hip_stream);
+
+/*
+ * Host tables of a lattice: cdirs [q][3] integer directions in the order
+ * documented above, w [q] equilibrium weights.  No HIP call.
+ */
+int lbmrv_lattice_tables(int lattice, int32_t *cdirs, double *w);
+
+void lbmrv_destroy(lbmrv_ctx *c);
+const char *lbmrv_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBMRV_H */

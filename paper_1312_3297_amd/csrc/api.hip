@@ -1,0 +1,412 @@
+// C-ABI layer of liblbmrv: argument validation, context, call sequencing.
+//
+// Host code only, apart from the final deterministic reduction kernel of
+// lbmrv_conservation.  Validation happens before any HIP call.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+
+#include "../../include/lbmrv.h"
+#include "launch.hpp"
+
+namespace lbmrv {
+
+__global__ __launch_bounds__(kRedThreads) void k_conserve_final(const double* partial, double* out) {
+  __shared__ double red[5][kRedThreads];
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < kRedBlocks; b += kRedThreads)
+    for (int i = 0; i < 5; ++i) acc[i] += partial[(uint64_t)b * 5 + i];
+  for (int i = 0; i < 5; ++i) red[i][threadIdx.x] = acc[i];
+  __syncthreads();
+  for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int i = 0; i < 5; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 5) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+namespace {
+
+using StepFn = hipError_t (*)(const StepLaunch&);
+using MomFn = hipError_t (*)(const MomLaunch&);
+using ConsFn = hipError_t (*)(const void*, uint64_t, double*, hipStream_t);
+using InitFn = hipError_t (*)(const InitLaunch&);
+using ConvFn = hipError_t (*)(const void*, void*, double, uint64_t, int, hipStream_t);
+
+struct Entry {
+  StepFn step[3];
+  MomFn mom[3];
+  ConsFn cons[3];
+  InitFn init[3];
+  ConvFn conv[3];
+};
+
+#define LBMRV_ENTRY(NAME)                                                                 \
+  Entry {                                                                                 \
+    {launch_step_##NAME##_f64, launch_step_##NAME##_f32, launch_step_##NAME##_f16},       \
+        {launch_moments_##NAME##_f64, launch_moments_##NAME##_f32, launch_moments_##NAME##_f16}, \
+        {launch_conserve_##NAME##_f64, launch_conserve_##NAME##_f32, launch_conserve_##NAME##_f16}, \
+        {launch_init_##NAME##_f64, launch_init_##NAME##_f32, launch_init_##NAME##_f16},   \
+        {launch_convert_##NAME##_f64, launch_convert_##NAME##_f32, launch_convert_##NAME##_f16} \
+  }
+
+const Entry kEntries[4] = {LBMRV_ENTRY(d2q9_paper), LBMRV_ENTRY(d2q9_geier), LBMRV_ENTRY(d3q19),
+                           LBMRV_ENTRY(d3q27)};
+
+}  // namespace
+}  // namespace lbmrv
+
+using namespace lbmrv;
+
+struct lbmrv_ctx {
+  int lattice, basis, storage;
+  int d, q;
+  int entry;      // index into kEntries
+  int sk;         // StorageKind
+  int streaming;  // LBMRV_STREAM_*
+  int block;
+  double lambda;
+  double s[27];
+  uint32_t nx, ny, nz;
+  uint64_t N;
+  double rho0;    // 0 unless a deviation storage
+  double* partial = nullptr;  // kRedBlocks * 5 partial sums + 5 results (device)
+  int partial_dev = -1;
+};
+
+namespace {
+
+int lattice_q(int lattice) { return lattice == LBMRV_D2Q9 ? 9 : lattice == LBMRV_D3Q19 ? 19 : 27; }
+int lattice_d(int lattice) { return lattice == LBMRV_D2Q9 ? 2 : 3; }
+size_t elem_bytes(int storage) { return storage == LBMRV_F64 ? 8 : storage == LBMRV_F16DEV ? 2 : 4; }
+
+int check_rates(int q, int d, const double* s) {
+  if (!s) return LBMRV_ERR_INVALID_ARG;
+  for (int k = 0; k < q; ++k) {
+    if (!std::isfinite(s[k])) return LBMRV_ERR_INVALID_ARG;
+    if (k <= d && s[k] != 0.0) return LBMRV_ERR_INVALID_ARG;  // conserved moments: s_k = 0
+    if (s[k] < 0.0 || s[k] > 2.0) return LBMRV_ERR_INVALID_ARG;
+  }
+  return LBMRV_OK;
+}
+
+int check_ptr(const void* p, size_t align) {
+  if (!p) return LBMRV_ERR_INVALID_ARG;
+  if (reinterpret_cast<uintptr_t>(p) % align) return LBMRV_ERR_ALIGNMENT;
+  return LBMRV_OK;
+}
+
+int check_mode(const lbmrv_ctx* c, int ut_mode, double ut_alpha, const float* ut_field) {
+  if (ut_mode != LBMRV_UT_ZERO && ut_mode != LBMRV_UT_FLUID && ut_mode != LBMRV_UT_FIELD)
+    return LBMRV_ERR_INVALID_ARG;
+  if (!std::isfinite(ut_alpha)) return LBMRV_ERR_INVALID_ARG;
+  if (ut_mode == LBMRV_UT_FIELD) return check_ptr(ut_field, 4);
+  (void)c;
+  return LBMRV_OK;
+}
+
+StepLaunch base_launch(const lbmrv_ctx* c, hipStream_t st) {
+  StepLaunch L{};
+  L.sk = c->sk;
+  L.nx = c->nx;
+  L.ny = c->ny;
+  L.nz = c->nz;
+  L.N = c->N;
+  L.rho0 = c->rho0;
+  L.alpha = 0;
+  L.inv_lambda = 1.0 / c->lambda;
+  for (int k = 0; k < 27; ++k) L.s[k] = k < c->q ? c->s[k] : 0.0;
+  L.stream = st;
+  L.block = c->block;
+  return L;
+}
+
+hipError_t run_kind(const lbmrv_ctx* c, int kind, const void* fin, void* fout, int mode, double alpha,
+                    const float* ut, hipStream_t st) {
+  StepLaunch L = base_launch(c, st);
+  L.kind = kind;
+  L.mode = mode;
+  L.alpha = alpha;
+  L.fin = fin;
+  L.fout = fout;
+  L.ut = ut;
+  return kEntries[c->entry].step[c->sk](L);
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbmrv_create(lbmrv_ctx** out, int lattice, int basis, double lambda, const double* s, const int64_t* dims,
+                 int storage, double rho0) {
+  if (!out) return LBMRV_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (lattice != LBMRV_D2Q9 && lattice != LBMRV_D3Q19 && lattice != LBMRV_D3Q27) return LBMRV_ERR_INVALID_ARG;
+  if (basis != LBMRV_BASIS_DEFAULT && basis != LBMRV_BASIS_GEIER) return LBMRV_ERR_INVALID_ARG;
+  if (basis == LBMRV_BASIS_GEIER && lattice != LBMRV_D2Q9) return LBMRV_ERR_INVALID_ARG;
+  if (!(std::isfinite(lambda) && lambda > 0.0)) return LBMRV_ERR_INVALID_ARG;
+  if (storage < LBMRV_F64 || storage > LBMRV_F16DEV) return LBMRV_ERR_INVALID_ARG;
+  if (!std::isfinite(rho0)) return LBMRV_ERR_INVALID_ARG;
+  const int q = lattice_q(lattice), d = lattice_d(lattice);
+  int rc = check_rates(q, d, s);
+  if (rc) return rc;
+  if (!dims) return LBMRV_ERR_INVALID_ARG;
+  uint64_t e[3] = {1, 1, 1};
+  for (int a = 0; a < d; ++a) {
+    if (dims[a] < 1 || dims[a] > 65535 * 4096LL) return LBMRV_ERR_INVALID_ARG;
+    e[a] = (uint64_t)dims[a];
+  }
+  if (e[1] > 65535 || e[2] > 65535) return LBMRV_ERR_INVALID_ARG;  // grid y/z limits
+  const uint64_t N = e[0] * e[1] * e[2];
+  if (N * (uint64_t)q >= (1ull << 32)) return LBMRV_ERR_INVALID_ARG;
+  lbmrv_ctx* c = new (std::nothrow) lbmrv_ctx();
+  if (!c) return LBMRV_ERR_INVALID_ARG;
+  c->lattice = lattice;
+  c->basis = basis;
+  c->storage = storage;
+  c->q = q;
+  c->d = d;
+  c->entry = lattice == LBMRV_D2Q9 ? (basis == LBMRV_BASIS_GEIER ? 1 : 0) : lattice == LBMRV_D3Q19 ? 2 : 3;
+  c->sk = storage == LBMRV_F64 ? SK_F64 : storage == LBMRV_F16DEV ? SK_F16 : SK_F32;
+  c->streaming = LBMRV_STREAM_PULL;
+  c->block = 256;
+  c->lambda = lambda;
+  for (int k = 0; k < 27; ++k) c->s[k] = k < q ? s[k] : 0.0;
+  c->nx = (uint32_t)e[0];
+  c->ny = (uint32_t)e[1];
+  c->nz = (uint32_t)e[2];
+  c->N = N;
+  c->rho0 = (storage == LBMRV_F32DEV || storage == LBMRV_F16DEV) ? rho0 : 0.0;
+  *out = c;
+  return LBMRV_OK;
+}
+
+int lbmrv_set_rates(lbmrv_ctx* c, const double* s) {
+  if (!c) return LBMRV_ERR_INVALID_ARG;
+  int rc = check_rates(c->q, c->d, s);
+  if (rc) return rc;
+  for (int k = 0; k < c->q; ++k) c->s[k] = s[k];
+  return LBMRV_OK;
+}
+
+int lbmrv_set_streaming(lbmrv_ctx* c, int kind) {
+  if (!c || (kind != LBMRV_STREAM_PULL && kind != LBMRV_STREAM_PUSH)) return LBMRV_ERR_INVALID_ARG;
+  c->streaming = kind;
+  return LBMRV_OK;
+}
+
+int lbmrv_info(const lbmrv_ctx* c, int64_t* q, int64_t* d, int64_t* nodes, int64_t* bytes_per_pop) {
+  if (!c) return LBMRV_ERR_INVALID_ARG;
+  if (q) *q = c->q;
+  if (d) *d = c->d;
+  if (nodes) *nodes = (int64_t)c->N;
+  if (bytes_per_pop) *bytes_per_pop = (int64_t)elem_bytes(c->storage);
+  return LBMRV_OK;
+}
+
+int lbmrv_step(lbmrv_ctx* c, void* f_in, void* f_out, int ut_mode, double ut_alpha, const float* ut_field,
+               int64_t nsteps, void* hip_stream) {
+  if (!c) return LBMRV_ERR_INVALID_ARG;
+  const size_t eb = elem_bytes(c->storage);
+  int rc;
+  if ((rc = check_ptr(f_in, eb)) || (rc = check_ptr(f_out, eb))) return rc;
+  if (f_in == f_out || nsteps < 0) return LBMRV_ERR_INVALID_ARG;
+  if ((rc = check_mode(c, ut_mode, ut_alpha, ut_field))) return rc;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (nsteps == 0) {
+    return hipMemcpyAsync(f_out, f_in, eb * c->q * c->N, hipMemcpyDeviceToDevice, st) == hipSuccess
+               ? LBMRV_OK
+               : LBMRV_ERR_HIP;
+  }
+  hipError_t e = hipSuccess;
+  if (c->streaming == LBMRV_STREAM_PUSH) {
+    // Pre-collision state throughout: one fused collide-and-scatter pass per
+    // step.  Out-of-place passes alternate between the two buffers, so an odd
+    // number of them must run to end in f_out.  For even nsteps the first step
+    // is split into an out-of-place collision (f_in -> f_out) and a transport
+    // (f_out -> f_in), which adds one pass.
+    void* cur = f_in;
+    int64_t i0 = 0;
+    if (nsteps % 2 == 0) {
+      e = run_kind(c, K_COLLIDE, f_in, f_out, ut_mode, ut_alpha, ut_field, st);
+      if (e == hipSuccess) e = run_kind(c, K_STREAM, f_out, f_in, LBMRV_UT_ZERO, 0.0, nullptr, st);
+      if (e != hipSuccess) return LBMRV_ERR_HIP;
+      i0 = 1;
+    }
+    for (int64_t i = i0; i < nsteps; ++i) {
+      void* nxt = (cur == f_in) ? f_out : f_in;
+      e = run_kind(c, K_PUSH, cur, nxt, ut_mode, ut_alpha, ut_field, st);
+      if (e != hipSuccess) return LBMRV_ERR_HIP;
+      cur = nxt;
+    }
+    return LBMRV_OK;
+  }
+  // Pull: collide once at the start, then nsteps - 1 fused transport+collide
+  // passes, then one transport.  The out-of-place passes alternate buffers and
+  // the last one writes f_out; the first collision is in place when nsteps is
+  // odd and f_in -> f_out when it is even.
+  void* cur;
+  if (nsteps % 2 == 1) {
+    e = run_kind(c, K_COLLIDE, f_in, f_in, ut_mode, ut_alpha, ut_field, st);
+    cur = f_in;
+  } else {
+    e = run_kind(c, K_COLLIDE, f_in, f_out, ut_mode, ut_alpha, ut_field, st);
+    cur = f_out;
+  }
+  if (e != hipSuccess) return LBMRV_ERR_HIP;
+  for (int64_t i = 1; i < nsteps; ++i) {
+    void* nxt = (cur == f_in) ? f_out : f_in;
+    e = run_kind(c, K_PULL, cur, nxt, ut_mode, ut_alpha, ut_field, st);
+    if (e != hipSuccess) return LBMRV_ERR_HIP;
+    cur = nxt;
+  }
+  void* nxt = (cur == f_in) ? f_out : f_in;
+  e = run_kind(c, K_STREAM, cur, nxt, LBMRV_UT_ZERO, 0.0, nullptr, st);
+  return e == hipSuccess ? LBMRV_OK : LBMRV_ERR_HIP;
+}
+
+int lbmrv_collide(lbmrv_ctx* c, const void* f_in, void* f_out, int ut_mode, double ut_alpha, const float* ut_field,
+                  void* hip_stream) {
+  if (!c) return LBMRV_ERR_INVALID_ARG;
+  const size_t eb = elem_bytes(c->storage);
+  int rc;
+  if ((rc = check_ptr(f_in, eb)) || (rc = check_ptr(f_out, eb))) return rc;
+  if ((rc = check_mode(c, ut_mode, ut_alpha, ut_field))) return rc;
+  hipError_t e = run_kind(c, K_COLLIDE, f_in, f_out, ut_mode, ut_alpha, ut_field, static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? LBMRV_OK : LBMRV_ERR_HIP;
+}
+
+int lbmrv_transport(lbmrv_ctx* c, const void* f_in, void* f_out, void* hip_stream) {
+  if (!c) return LBMRV_ERR_INVALID_ARG;
+  const size_t eb = elem_bytes(c->storage);
+  int rc;
+  if ((rc = check_ptr(f_in, eb)) || (rc = check_ptr(f_out, eb))) return rc;
+  if (f_in == f_out) return LBMRV_ERR_INVALID_ARG;
+  hipError_t e = run_kind(c, K_STREAM, f_in, f_out, LBMRV_UT_ZERO, 0.0, nullptr, static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? LBMRV_OK : LBMRV_ERR_HIP;
+}
+
+int lbmrv_moments(lbmrv_ctx* c, const void* f, void* rho, void* u, void* m0, void* hip_stream) {
+  if (!c) return LBMRV_ERR_INVALID_ARG;
+  const size_t eb = elem_bytes(c->storage);
+  const size_t ob = c->storage == LBMRV_F64 ? 8 : 4;
+  int rc;
+  if ((rc = check_ptr(f, eb)) || (rc = check_ptr(rho, ob)) || (rc = check_ptr(u, ob))) return rc;
+  if (m0 && (rc = check_ptr(m0, ob))) return rc;
+  MomLaunch L{};
+  L.sk = c->sk;
+  L.f = f;
+  L.rho = rho;
+  L.u = u;
+  L.m0 = m0;
+  L.N = c->N;
+  L.rho0 = c->rho0;
+  L.lambda = c->lambda;
+  L.stream = static_cast<hipStream_t>(hip_stream);
+  return kEntries[c->entry].mom[c->sk](L) == hipSuccess ? LBMRV_OK : LBMRV_ERR_HIP;
+}
+
+int lbmrv_conservation(lbmrv_ctx* c, const void* f, double out[4], void* hip_stream) {
+  if (!c || !out) return LBMRV_ERR_INVALID_ARG;
+  int rc;
+  if ((rc = check_ptr(f, elem_bytes(c->storage)))) return rc;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return LBMRV_ERR_HIP;
+  if (c->partial && c->partial_dev != dev) return LBMRV_ERR_INVALID_ARG;  // context bound to its first device
+  if (!c->partial) {
+    if (hipMalloc(&c->partial, sizeof(double) * (kRedBlocks * 5 + 8)) != hipSuccess) {
+      c->partial = nullptr;
+      return LBMRV_ERR_HIP;
+    }
+    c->partial_dev = dev;
+  }
+  if (kEntries[c->entry].cons[c->sk](f, c->N, c->partial, st) != hipSuccess) return LBMRV_ERR_HIP;
+  double* res = c->partial + kRedBlocks * 5;
+  hipLaunchKernelGGL(k_conserve_final, dim3(1), dim3(kRedThreads), 0, st, c->partial, res);
+  if (hipGetLastError() != hipSuccess) return LBMRV_ERR_HIP;
+  double h[5];
+  if (hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess) return LBMRV_ERR_HIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return LBMRV_ERR_HIP;
+  // sum of the stored values; deviation storage adds back rho0 * N (sum of w_j = 1,
+  // sum of w_j c_j = 0)
+  out[0] = h[0] + c->rho0 * (double)c->N;
+  for (int a = 0; a < 3; ++a) out[1 + a] = a < c->d ? c->lambda * h[1 + a] : 0.0;
+  return h[4] > 0 ? LBMRV_ERR_NONFINITE : LBMRV_OK;
+}
+
+int lbmrv_init_equilibrium(lbmrv_ctx* c, const double* rho, const double* u, const double* noise, double noise_amp,
+                           void* f_out, void* hip_stream) {
+  if (!c) return LBMRV_ERR_INVALID_ARG;
+  int rc;
+  if ((rc = check_ptr(rho, 8)) || (rc = check_ptr(u, 8)) || (rc = check_ptr(f_out, elem_bytes(c->storage)))) return rc;
+  if (noise && (rc = check_ptr(noise, 8))) return rc;
+  if (!std::isfinite(noise_amp)) return LBMRV_ERR_INVALID_ARG;
+  InitLaunch L{};
+  L.rho = rho;
+  L.u = u;
+  L.noise = noise;
+  L.amp = noise_amp;
+  L.rho0 = c->rho0;
+  L.lambda = c->lambda;
+  L.N = c->N;
+  L.fout = f_out;
+  L.stream = static_cast<hipStream_t>(hip_stream);
+  return kEntries[c->entry].init[c->sk](L) == hipSuccess ? LBMRV_OK : LBMRV_ERR_HIP;
+}
+
+static int convert(lbmrv_ctx* c, const void* in, void* out, int to_storage, void* hip_stream) {
+  if (!c) return LBMRV_ERR_INVALID_ARG;
+  const size_t eb = elem_bytes(c->storage);
+  int rc;
+  if ((rc = check_ptr(in, to_storage ? 8 : eb)) || (rc = check_ptr(out, to_storage ? eb : 8))) return rc;
+  return kEntries[c->entry].conv[c->sk](in, out, c->rho0, c->N, to_storage, static_cast<hipStream_t>(hip_stream)) ==
+                 hipSuccess
+             ? LBMRV_OK
+             : LBMRV_ERR_HIP;
+}
+
+int lbmrv_import(lbmrv_ctx* c, const double* f, void* out, void* hip_stream) { return convert(c, f, out, 1, hip_stream); }
+int lbmrv_export(lbmrv_ctx* c, const void* in, double* f, void* hip_stream) { return convert(c, in, f, 0, hip_stream); }
+
+int lbmrv_lattice_tables(int lattice, int32_t* cdirs, double* w) {
+  if (lattice != LBMRV_D2Q9 && lattice != LBMRV_D3Q19 && lattice != LBMRV_D3Q27) return LBMRV_ERR_INVALID_ARG;
+  if (!cdirs || !w) return LBMRV_ERR_INVALID_ARG;
+  auto fill = [&](auto lat) {
+    using L = decltype(lat);
+    for (int j = 0; j < L::Q; ++j) {
+      cdirs[3 * j] = L::c[j].x;
+      cdirs[3 * j + 1] = L::c[j].y;
+      cdirs[3 * j + 2] = L::c[j].z;
+      w[j] = L::w(j).val();
+    }
+  };
+  if (lattice == LBMRV_D2Q9) fill(D2Q9Lat{});
+  else if (lattice == LBMRV_D3Q19) fill(D3Q19Lat{});
+  else fill(D3Q27Lat{});
+  return LBMRV_OK;
+}
+
+void lbmrv_destroy(lbmrv_ctx* c) {
+  if (!c) return;
+  if (c->partial) (void)hipFree(c->partial);
+  delete c;
+}
+
+const char* lbmrv_strerror(int code) {
+  switch (code) {
+    case LBMRV_OK: return "ok";
+    case LBMRV_ERR_INVALID_ARG: return "invalid argument";
+    case LBMRV_ERR_UNSUPPORTED: return "unsupported request";
+    case LBMRV_ERR_HIP: return "HIP runtime error";
+    case LBMRV_ERR_NONFINITE: return "non-finite population found";
+    case LBMRV_ERR_ALIGNMENT: return "pointer not aligned to its element size";
+  }
+  return "unknown error code";
+}
+
+}  // extern "C"

@@ -1,0 +1,407 @@
+// HIP kernels of the relative-velocity lattice Boltzmann step (gfx950).
+//
+// One thread owns one lattice node per pass.  The per-node algebra (moments,
+// shift into the moving frame, diagonal relaxation, shift back, inversion) is
+// unrolled at compile time over the exact tables of tables.hpp and lives in
+// registers; it is a handful of sparse q-vectors per node, not a contraction,
+// so no matrix cores are involved.  Populations are SoA: f[j][z][y][x] with x
+// fastest, so each population access of a wavefront is one contiguous run.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <utility>
+
+#include "tables.hpp"
+
+namespace lbmrv {
+
+// ------------------------------------------------------------------ helpers
+template <class F, int... I>
+__device__ __forceinline__ void sfor_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+// static_for: calls f(integral_constant<int, i>) for i = 0 .. N-1
+template <int N, class F>
+__device__ __forceinline__ void sfor(F&& f) {
+  sfor_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+template <class T>
+__device__ __forceinline__ T fmac(T a, T b, T c) {
+  if constexpr (sizeof(T) == 4) return __builtin_fmaf(a, b, c);
+  else return __builtin_fma(a, b, c);
+}
+
+// y += C * x for a compile-time rational C (folds +-1 to add / sub)
+template <Rat C, class T>
+__device__ __forceinline__ void axpy_c(T& y, T x) {
+  constexpr T cv = T(C.val());
+  if constexpr (C == Rat(1)) y += x;
+  else if constexpr (C == Rat(-1)) y -= x;
+  else y = fmac(cv, x, y);
+}
+
+template <Rat C, class T>
+__device__ __forceinline__ constexpr T lit() {
+  return T(C.val());
+}
+
+// storage element types
+template <int ST>
+struct Store;
+template <>
+struct Store<0> { using S = double; using T = double; };   // FP64
+template <>
+struct Store<1> { using S = float; using T = float; };     // FP32 (also FP32 deviations)
+template <>
+struct Store<2> { using S = _Float16; using T = float; };  // FP16 deviations, FP32 arithmetic
+
+enum Mode { UT_ZERO = 0, UT_FLUID = 1, UT_FIELD = 2 };
+enum Kind { K_PULL = 0, K_PUSH = 1, K_COLLIDE = 2, K_STREAM = 3 };
+
+template <class T>
+struct StepArgs {
+  const void* fin;
+  void* fout;
+  const float* ut;  // [d][N] relative-velocity field (physical units) or null
+  uint32_t nx, ny, nz;
+  uint64_t N;       // nodes
+  T rho0;           // reference density subtracted in deviation storage (0 otherwise)
+  T alpha;          // FLUID mode: u~ = alpha u
+  T inv_lambda;     // FIELD mode: u~ is given in physical units
+  T s[27];          // relaxation rates of the user basis
+};
+
+// ------------------------------------------------------------------ collision
+// In-register collision at one node.  h holds the populations minus w_j rho0.
+// After return h holds the post-collision values (same offset).
+template <class B, class T, int MODE>
+__device__ __forceinline__ void collide_node(T (&h)[B::Q], const StepArgs<T>& a, const T (&utf)[3]) {
+  using L = typename B::Lat;
+  constexpr int Q = B::Q;
+  constexpr int D = L::D;
+  using Tb = Tab<B>;
+
+  // conserved moments, eq. (rhoq): rho = rho0 + sum h, j = sum c h
+  T drho = h[0];
+  sfor<Q - 1>([&](auto jj) { drho += h[jj + 1]; });
+  T jm[3] = {T(0), T(0), T(0)};
+  sfor<Q>([&](auto jj) {
+    constexpr int J = jj;
+    if constexpr (L::c[J].x > 0) jm[0] += h[J];
+    if constexpr (L::c[J].x < 0) jm[0] -= h[J];
+    if constexpr (L::c[J].y > 0) jm[1] += h[J];
+    if constexpr (L::c[J].y < 0) jm[1] -= h[J];
+    if constexpr (L::c[J].z > 0) jm[2] += h[J];
+    if constexpr (L::c[J].z < 0) jm[2] -= h[J];
+  });
+  const T rho = a.rho0 + drho;
+  const T irho = T(1) / rho;
+  T u[3] = {jm[0] * irho, jm[1] * irho, D == 3 ? jm[2] * irho : T(0)};
+
+  // relative velocity
+  T ut[3] = {T(0), T(0), T(0)};
+  if constexpr (MODE == UT_FLUID) {
+    sfor<D>([&](auto al) { ut[al] = a.alpha * u[al]; });
+  } else if constexpr (MODE == UT_FIELD) {
+    sfor<D>([&](auto al) { ut[al] = utf[al]; });
+  }
+
+  // fixed-frame non-equilibrium moments in the working basis (k > d only;
+  // the conserved entries are exactly zero because f^eq has the same rho, j)
+  T dl[Q];
+  sfor<Q>([&](auto kk) {
+    constexpr int K = kk;
+    if constexpr (K <= D) {
+      dl[K] = T(0);
+    } else {
+      T mh = T(0);
+      sfor<Tb::t.sMW[K].n>([&](auto i) {
+        axpy_c<Tb::t.sMW[K].val[i]>(mh, h[Tb::t.sMW[K].col[i]]);
+      });
+      T quad = T(0);
+      sfor<D>([&](auto al) {
+        constexpr Rat bb = Tb::t.b[K][al];
+        if constexpr (!bb.zero()) quad = fmac(lit<bb, T>(), u[al], quad);
+        sfor<D>([&](auto be) {
+          if constexpr (be >= al) {
+            constexpr Rat cc = (be == al) ? Tb::t.C[K][al][be] : Tb::t.C[K][al][be] + Tb::t.C[K][be][al];
+            if constexpr (!cc.zero()) quad = fmac(lit<cc, T>() * u[al], u[be], quad);
+          }
+        });
+      });
+      T eq = rho * quad;
+      constexpr Rat ak = Tb::t.a[K];
+      if constexpr (!ak.zero()) eq = fmac(lit<ak, T>(), drho, eq);
+      dl[K] = eq - mh;
+    }
+  });
+
+  // shift into the frame moving at u~:  dl <- prod_a exp(-u~_a D_a) dl
+  auto shift = [&](T sign) {
+    sfor<D>([&](auto ax) {
+      constexpr int AX = ax;
+      constexpr int NM = Tb::t.nmax[AX];
+      T pw[kP];
+      pw[1] = sign * ut[AX];
+      sfor<NM>([&](auto nn) {
+        if constexpr (nn + 1 >= 2) pw[nn + 1] = pw[nn] * pw[1];
+      });
+      T out[Q];
+      sfor<Q>([&](auto kk) {
+        constexpr int K = kk;
+        out[K] = dl[K];
+        if constexpr (K > D) {
+          sfor<NM>([&](auto nn) {
+            constexpr int N = nn + 1;
+            constexpr int NZ = Tb::t.sE[AX][N][K].n;
+            if constexpr (NZ > 0) {
+              T acc = T(0);
+              sfor<NZ>([&](auto i) {
+                axpy_c<Tb::t.sE[AX][N][K].val[i]>(acc, dl[Tb::t.sE[AX][N][K].col[i]]);
+              });
+              out[K] = fmac(pw[N], acc, out[K]);
+            }
+          });
+        }
+      });
+      sfor<Q>([&](auto kk) { dl[kk] = out[kk]; });
+    });
+  };
+  if constexpr (MODE != UT_ZERO) shift(T(-1));
+
+  // diagonal relaxation in the user basis, eq. (relaxationu): r = Rinv S R dl
+  {
+    T r[Q];
+    sfor<Q>([&](auto kk) {
+      constexpr int K = kk;
+      if constexpr (K > D) {
+        T acc = T(0);
+        sfor<Tb::t.sR[K].n>([&](auto i) { axpy_c<Tb::t.sR[K].val[i]>(acc, dl[Tb::t.sR[K].col[i]]); });
+        r[K] = acc * a.s[K];
+      } else {
+        r[K] = T(0);
+      }
+    });
+    sfor<Q>([&](auto kk) {
+      constexpr int K = kk;
+      if constexpr (K > D) {
+        T acc = T(0);
+        sfor<Tb::t.sRinv[K].n>([&](auto i) { axpy_c<Tb::t.sRinv[K].val[i]>(acc, r[Tb::t.sRinv[K].col[i]]); });
+        dl[K] = acc;
+      }
+    });
+  }
+
+  // shift back: T(u~)^{-1} = T(-u~) (Prop. th:csd2q9)
+  if constexpr (MODE != UT_ZERO) shift(T(1));
+
+  // back to populations: h += M_W(0)^{-1} dm  (dm vanishes on the conserved block)
+  sfor<Q>([&](auto jj) {
+    constexpr int J = jj;
+    T acc = T(0);
+    sfor<Tb::t.sMWinv[J].n>([&](auto i) { axpy_c<Tb::t.sMWinv[J].val[i]>(acc, dl[Tb::t.sMWinv[J].col[i]]); });
+    h[J] += acc;
+  });
+}
+
+// ------------------------------------------------------------------ step kernel
+// Grid: (ceil(nx / blockDim.x), ny, nz).  One thread = one node (x, y, z).
+template <class B, int ST, int MODE, int KIND>
+__global__ __launch_bounds__(256) void k_step(StepArgs<typename Store<ST>::T> a) {
+  using L = typename B::Lat;
+  using S = typename Store<ST>::S;
+  using T = typename Store<ST>::T;
+  constexpr int Q = B::Q;
+  constexpr int D = L::D;
+
+  const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t y = blockIdx.y, z = blockIdx.z;
+  if (x >= a.nx) return;
+  const uint32_t nx = a.nx, ny = a.ny, nz = a.nz;
+  const uint32_t xm = x == 0 ? nx - 1 : x - 1;
+  const uint32_t xp = x == nx - 1 ? 0 : x + 1;
+  const uint32_t ym = y == 0 ? ny - 1 : y - 1;
+  const uint32_t yp = y == ny - 1 ? 0 : y + 1;
+  const uint32_t zm = z == 0 ? nz - 1 : z - 1;
+  const uint32_t zp = z == nz - 1 ? 0 : z + 1;
+  const uint32_t own = (z * ny + y) * nx + x;
+
+  // node offset of x + dir * c_j (dir = -1: upstream for pull, +1: downstream for push)
+  auto nbr = [&](auto jj, auto dirc) -> uint32_t {
+    constexpr int J = jj;
+    constexpr int dir = dirc;
+    constexpr int cx = dir * L::c[J].x, cy = dir * L::c[J].y, cz = dir * L::c[J].z;
+    const uint32_t xx = cx == 0 ? x : (cx > 0 ? xp : xm);
+    const uint32_t yy = cy == 0 ? y : (cy > 0 ? yp : ym);
+    const uint32_t zz = cz == 0 ? z : (cz > 0 ? zp : zm);
+    return (zz * ny + yy) * nx + xx;
+  };
+
+  const S* fin = static_cast<const S*>(a.fin);  // may alias fout for in-place collision
+  S* fout = static_cast<S*>(a.fout);
+  const uint64_t N = a.N;
+
+  T h[Q];
+  sfor<Q>([&](auto jj) {
+    constexpr int J = jj;
+    uint32_t src = own;
+    if constexpr (KIND == K_PULL || KIND == K_STREAM) src = nbr(jj, std::integral_constant<int, -1>{});
+    h[J] = T(fin[(uint64_t)J * N + src]);
+  });
+
+  if constexpr (KIND != K_STREAM) {
+    T utf[3] = {T(0), T(0), T(0)};
+    if constexpr (MODE == UT_FIELD) {
+      sfor<D>([&](auto al) { utf[al] = T(a.ut[(uint64_t)al * N + own]) * a.inv_lambda; });
+    }
+    collide_node<B, T, MODE>(h, a, utf);
+  }
+
+  sfor<Q>([&](auto jj) {
+    constexpr int J = jj;
+    uint32_t dst = own;
+    if constexpr (KIND == K_PUSH) dst = nbr(jj, std::integral_constant<int, 1>{});
+    fout[(uint64_t)J * N + dst] = S(h[J]);
+  });
+}
+
+// ------------------------------------------------------------------ moments
+template <class T>
+struct MomArgs {
+  const void* f;
+  void* rho;   // [N]
+  void* u;     // [d][N]
+  void* m0;    // [q][N] or null
+  uint64_t N;
+  T rho0, lambda;
+};
+
+// rho, u (physical units) and optionally the fixed-frame user moments
+// m(0) = M(0) f (eq. (matort) for the D2Q9 paper basis), all per node.
+template <class B, int ST>
+__global__ __launch_bounds__(256) void k_moments(MomArgs<typename Store<ST>::T> a) {
+  using L = typename B::Lat;
+  using S = typename Store<ST>::S;
+  using T = typename Store<ST>::T;
+  using O = T;  // output element type
+  constexpr int Q = B::Q;
+  constexpr int D = L::D;
+  using Tb = Tab<B>;
+  const uint64_t n = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= a.N) return;
+  const S* f = static_cast<const S*>(a.f);
+  T h[Q];
+  sfor<Q>([&](auto jj) { h[jj] = T(f[(uint64_t)jj * a.N + n]); });
+  T drho = h[0];
+  sfor<Q - 1>([&](auto jj) { drho += h[jj + 1]; });
+  T jm[3] = {T(0), T(0), T(0)};
+  sfor<Q>([&](auto jj) {
+    constexpr int J = jj;
+    if constexpr (L::c[J].x != 0) jm[0] += T(L::c[J].x) * h[J];
+    if constexpr (L::c[J].y != 0) jm[1] += T(L::c[J].y) * h[J];
+    if constexpr (L::c[J].z != 0) jm[2] += T(L::c[J].z) * h[J];
+  });
+  const T rho = a.rho0 + drho;
+  static_cast<O*>(a.rho)[n] = O(rho);
+  sfor<D>([&](auto al) { static_cast<O*>(a.u)[(uint64_t)al * a.N + n] = O(a.lambda * jm[al] / rho); });
+  if (a.m0) {
+    sfor<Q>([&](auto kk) {
+      constexpr int K = kk;
+      T acc = T(0);
+      sfor<Tb::t.sMP[K].n>([&](auto i) { axpy_c<Tb::t.sMP[K].val[i]>(acc, h[Tb::t.sMP[K].col[i]]); });
+      constexpr Rat restK = Tb::t.restP[K];
+      if constexpr (!restK.zero()) acc = fmac(lit<restK, T>(), a.rho0, acc);
+      T sc = T(1);
+      sfor<Tb::t.lam_deg[K]>([&](auto) { sc *= a.lambda; });
+      static_cast<O*>(a.m0)[(uint64_t)K * a.N + n] = O(acc * sc);
+    });
+  }
+}
+
+// ------------------------------------------------------------------ initial state
+// f_j = f^eq_j(rho, u) + amp * noise_j in FP64 (equilibrium of section 1.2 with
+// the second-order polynomial form), stored minus w_j rho0 in the storage type.
+// rho [N], u [d][N] (physical units), noise [q][N] or null.
+template <class B, int ST>
+__global__ __launch_bounds__(256) void k_init_eq(const double* rho, const double* u, const double* noise, double amp,
+                                                 double rho0, double lambda, uint64_t N, void* fout) {
+  using L = typename B::Lat;
+  using S = typename Store<ST>::S;
+  using Tb = Tab<B>;
+  constexpr int Q = B::Q;
+  constexpr int D = L::D;
+  const uint64_t n = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const double r = rho[n];
+  double uu[3] = {0, 0, 0};
+  sfor<D>([&](auto al) { uu[al] = u[(uint64_t)al * N + n] / lambda; });
+  const double u2 = uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2];
+  S* f = static_cast<S*>(fout);
+  sfor<Q>([&](auto jj) {
+    constexpr int J = jj;
+    constexpr double w = Tb::t.w[J].val();
+    const double cu = double(L::c[J].x) * uu[0] + double(L::c[J].y) * uu[1] + double(L::c[J].z) * uu[2];
+    double fe = w * r * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * u2);
+    if (noise) fe += amp * noise[(uint64_t)J * N + n];
+    f[(uint64_t)J * N + n] = S(fe - w * rho0);
+  });
+}
+
+// Storage <-> FP64 conversion: f64 = stored + w_j rho0, stored = rn(f64 - w_j rho0).
+template <class B, int ST>
+__global__ __launch_bounds__(256) void k_convert(const void* in, void* out, double rho0, uint64_t N, int to_storage) {
+  using S = typename Store<ST>::S;
+  using Tb = Tab<B>;
+  constexpr int Q = B::Q;
+  const uint64_t n = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  sfor<Q>([&](auto jj) {
+    constexpr double w = Tb::t.w[jj].val();
+    const uint64_t i = (uint64_t)jj * N + n;
+    if (to_storage) static_cast<S*>(out)[i] = S(static_cast<const double*>(in)[i] - w * rho0);
+    else static_cast<double*>(out)[i] = double(static_cast<const S*>(in)[i]) + w * rho0;
+  });
+}
+
+// ------------------------------------------------------------------ conservation
+// FP64 block partial sums of (sum h, sum c h, non-finite count) per block.
+constexpr int kRedBlocks = 1024;
+constexpr int kRedThreads = 256;
+
+template <class B, int ST>
+__global__ __launch_bounds__(kRedThreads) void k_conserve_partial(const void* fp, uint64_t N, double* partial) {
+  using L = typename B::Lat;
+  using S = typename Store<ST>::S;
+  constexpr int Q = B::Q;
+  const S* f = static_cast<const S*>(fp);
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (uint64_t n = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (uint64_t)gridDim.x * blockDim.x) {
+    sfor<Q>([&](auto jj) {
+      constexpr int J = jj;
+      const double v = double(f[(uint64_t)J * N + n]);
+      if (!__builtin_isfinite(v)) acc[4] += 1.0;
+      acc[0] += v;
+      if constexpr (L::c[J].x != 0) acc[1] += double(L::c[J].x) * v;
+      if constexpr (L::c[J].y != 0) acc[2] += double(L::c[J].y) * v;
+      if constexpr (L::c[J].z != 0) acc[3] += double(L::c[J].z) * v;
+    });
+  }
+  __shared__ double red[5][kRedThreads];
+  for (int i = 0; i < 5; ++i) red[i][threadIdx.x] = acc[i];
+  __syncthreads();
+  for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int i = 0; i < 5; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int i = 0; i < 5; ++i) partial[(uint64_t)blockIdx.x * 5 + i] = red[i][0];
+}
+
+// Sums kRedBlocks partials in a fixed order (one block), deterministic.
+__global__ __launch_bounds__(kRedThreads) void k_conserve_final(const double* partial, double* out);
+
+}  // namespace lbmrv

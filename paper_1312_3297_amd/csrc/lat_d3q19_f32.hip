@@ -1,0 +1,6 @@
+// Kernel instantiations for the d3q19 lattice and basis, f32 storage.
+#include "launch.hpp"
+
+namespace lbmrv {
+LBMRV_DEFINE_LAUNCHERS(d3q19, BasisD3Q19, f32, 1)
+}  // namespace lbmrv

@@ -1,0 +1,164 @@
+// Host-side launchers for one (lattice, basis) pair.  Each per-lattice
+// translation unit instantiates these once; the C-ABI layer dispatches to them.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace lbmrv {
+
+enum StorageKind { SK_F64 = 0, SK_F32 = 1, SK_F16 = 2 };
+
+struct StepLaunch {
+  int sk;      // StorageKind
+  int mode;    // Mode
+  int kind;    // Kind
+  const void* fin;
+  void* fout;
+  const float* ut;
+  uint32_t nx, ny, nz;
+  uint64_t N;
+  double rho0, alpha, inv_lambda;
+  double s[27];
+  hipStream_t stream;
+  int block;   // threads per block along x
+};
+
+struct MomLaunch {
+  int sk;
+  const void* f;
+  void* rho;
+  void* u;
+  void* m0;
+  uint64_t N;
+  double rho0, lambda;
+  hipStream_t stream;
+};
+
+template <class B, int ST, int MODE, int KIND>
+hipError_t launch_step_t(const StepLaunch& L) {
+  using T = typename Store<ST>::T;
+  StepArgs<T> a{};
+  a.fin = L.fin;
+  a.fout = L.fout;
+  a.ut = L.ut;
+  a.nx = L.nx;
+  a.ny = L.ny;
+  a.nz = L.nz;
+  a.N = L.N;
+  a.rho0 = T(L.rho0);
+  a.alpha = T(L.alpha);
+  a.inv_lambda = T(L.inv_lambda);
+  for (int k = 0; k < 27; ++k) a.s[k] = T(L.s[k]);
+  const int bx = L.block;
+  dim3 grid((L.nx + bx - 1) / bx, L.ny, L.nz);
+  hipLaunchKernelGGL((k_step<B, ST, MODE, KIND>), grid, dim3(bx), 0, L.stream, a);
+  return hipGetLastError();
+}
+
+template <class B, int ST, int MODE>
+hipError_t launch_step_m(const StepLaunch& L) {
+  switch (L.kind) {
+    case K_PULL: return launch_step_t<B, ST, MODE, K_PULL>(L);
+    case K_PUSH: return launch_step_t<B, ST, MODE, K_PUSH>(L);
+    case K_COLLIDE: return launch_step_t<B, ST, MODE, K_COLLIDE>(L);
+    case K_STREAM: return launch_step_t<B, ST, UT_ZERO, K_STREAM>(L);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <class B, int ST>
+hipError_t launch_step_s(const StepLaunch& L) {
+  switch (L.mode) {
+    case UT_ZERO: return launch_step_m<B, ST, UT_ZERO>(L);
+    case UT_FLUID: return launch_step_m<B, ST, UT_FLUID>(L);
+    case UT_FIELD: return launch_step_m<B, ST, UT_FIELD>(L);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <class B, int ST>
+hipError_t launch_moments_t(const MomLaunch& L) {
+  using T = typename Store<ST>::T;
+  MomArgs<T> a{};
+  a.f = L.f;
+  a.rho = L.rho;
+  a.u = L.u;
+  a.m0 = L.m0;
+  a.N = L.N;
+  a.rho0 = T(L.rho0);
+  a.lambda = T(L.lambda);
+  const unsigned grid = (unsigned)((L.N + 255) / 256);
+  hipLaunchKernelGGL((k_moments<B, ST>), dim3(grid), dim3(256), 0, L.stream, a);
+  return hipGetLastError();
+}
+
+template <class B, int ST>
+hipError_t launch_conserve_partial(const void* f, uint64_t N, double* partial, hipStream_t st) {
+  hipLaunchKernelGGL((k_conserve_partial<B, ST>), dim3(kRedBlocks), dim3(kRedThreads), 0, st, f, N, partial);
+  return hipGetLastError();
+}
+
+struct InitLaunch {
+  const double* rho;
+  const double* u;
+  const double* noise;
+  double amp, rho0, lambda;
+  uint64_t N;
+  void* fout;
+  hipStream_t stream;
+};
+
+template <class B, int ST>
+hipError_t launch_init_t(const InitLaunch& L) {
+  const unsigned grid = (unsigned)((L.N + 255) / 256);
+  hipLaunchKernelGGL((k_init_eq<B, ST>), dim3(grid), dim3(256), 0, L.stream, L.rho, L.u, L.noise, L.amp, L.rho0, L.lambda,
+                     L.N, L.fout);
+  return hipGetLastError();
+}
+
+template <class B, int ST>
+hipError_t launch_convert_t(const void* in, void* out, double rho0, uint64_t N, int to_storage, hipStream_t st) {
+  const unsigned grid = (unsigned)((N + 255) / 256);
+  hipLaunchKernelGGL((k_convert<B, ST>), dim3(grid), dim3(256), 0, st, in, out, rho0, N, to_storage);
+  return hipGetLastError();
+}
+
+// Per-(lattice, basis, storage) entry points, defined in the lattice translation
+// units (one unit per lattice and storage type, so they compile in parallel).
+#define LBMRV_DECLARE_LAUNCHERS(NAME, SKN)                                                  \
+  hipError_t launch_step_##NAME##_##SKN(const StepLaunch& L);                               \
+  hipError_t launch_moments_##NAME##_##SKN(const MomLaunch& L);                             \
+  hipError_t launch_conserve_##NAME##_##SKN(const void* f, uint64_t N, double* partial,     \
+                                            hipStream_t st);                                \
+  hipError_t launch_init_##NAME##_##SKN(const InitLaunch& L);                               \
+  hipError_t launch_convert_##NAME##_##SKN(const void* in, void* out, double rho0, uint64_t N, \
+                                           int to_storage, hipStream_t st);
+
+#define LBMRV_DEFINE_LAUNCHERS(NAME, BASIS, SKN, ST)                                        \
+  hipError_t launch_step_##NAME##_##SKN(const StepLaunch& L) { return launch_step_s<BASIS, ST>(L); } \
+  hipError_t launch_moments_##NAME##_##SKN(const MomLaunch& L) {                            \
+    return launch_moments_t<BASIS, ST>(L);                                                  \
+  }                                                                                         \
+  hipError_t launch_conserve_##NAME##_##SKN(const void* f, uint64_t N, double* partial,     \
+                                            hipStream_t st) {                               \
+    return launch_conserve_partial<BASIS, ST>(f, N, partial, st);                           \
+  }                                                                                         \
+  hipError_t launch_init_##NAME##_##SKN(const InitLaunch& L) { return launch_init_t<BASIS, ST>(L); } \
+  hipError_t launch_convert_##NAME##_##SKN(const void* in, void* out, double rho0, uint64_t N, \
+                                           int to_storage, hipStream_t st) {               \
+    return launch_convert_t<BASIS, ST>(in, out, rho0, N, to_storage, st);                   \
+  }
+
+#define LBMRV_DECLARE_ALL(NAME) \
+  LBMRV_DECLARE_LAUNCHERS(NAME, f64) LBMRV_DECLARE_LAUNCHERS(NAME, f32) LBMRV_DECLARE_LAUNCHERS(NAME, f16)
+
+LBMRV_DECLARE_ALL(d2q9_paper)
+LBMRV_DECLARE_ALL(d2q9_geier)
+LBMRV_DECLARE_ALL(d3q19)
+LBMRV_DECLARE_ALL(d3q27)
+
+}  // namespace lbmrv

@@ -1,0 +1,200 @@
+"""ctypes binding of liblbmrv.so (the HIP library).  Argument marshalling only.
+
+Every call goes to the C ABI declared in include/lbmrv.h; the arithmetic of the
+scheme runs in the library's HIP kernels.  PyTorch supplies device memory and
+the current stream.  Loading fails loudly when the library has not been built.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblbmrv.so")
+
+OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_NONFINITE, ERR_ALIGNMENT = 0, -1, -2, -4, -5, -6
+LATTICES = {"d2q9": 0, "d3q19": 1, "d3q27": 2}
+BASES = {"default": 0, "geier": 1}
+STORAGES = {"f64": 0, "f32": 1, "f32dev": 2, "f16dev": 3}
+MODES = {"zero": 0, "fluid": 1, "field": 2}
+STREAMING = {"pull": 0, "push": 1}
+QD = {"d2q9": (9, 2), "d3q19": (19, 3), "d3q27": (27, 3)}
+
+_c_void_p = ctypes.c_void_p
+_c_int = ctypes.c_int
+_c_double = ctypes.c_double
+_c_int64 = ctypes.c_int64
+
+_SIGS = {
+    "lbmrv_create": (_c_int, [ctypes.POINTER(_c_void_p), _c_int, _c_int, _c_double, ctypes.POINTER(_c_double),
+                              ctypes.POINTER(_c_int64), _c_int, _c_double]),
+    "lbmrv_set_rates": (_c_int, [_c_void_p, ctypes.POINTER(_c_double)]),
+    "lbmrv_set_streaming": (_c_int, [_c_void_p, _c_int]),
+    "lbmrv_info": (_c_int, [_c_void_p] + [ctypes.POINTER(_c_int64)] * 4),
+    "lbmrv_step": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_int, _c_double, _c_void_p, _c_int64, _c_void_p]),
+    "lbmrv_collide": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_int, _c_double, _c_void_p, _c_void_p]),
+    "lbmrv_transport": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p]),
+    "lbmrv_moments": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
+    "lbmrv_conservation": (_c_int, [_c_void_p, _c_void_p, ctypes.POINTER(_c_double), _c_void_p]),
+    "lbmrv_init_equilibrium": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_double, _c_void_p,
+                                        _c_void_p]),
+    "lbmrv_import": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p]),
+    "lbmrv_export": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p]),
+    "lbmrv_lattice_tables": (_c_int, [_c_int, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_c_double)]),
+    "lbmrv_destroy": (None, [_c_void_p]),
+    "lbmrv_strerror": (ctypes.c_char_p, [_c_int]),
+}
+
+_lib = None
+
+
+def library():
+    """Load liblbmrv.so once; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError("liblbmrv.so not built: run __graft_entry__.build() "
+                              "(or python paper_1312_3297_amd/build.py) first")
+        lib = ctypes.CDLL(_LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class LbmrvError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        msg = library().lbmrv_strerror(code).decode()
+        super().__init__("%s failed: %s (%d)" % (what, msg, code))
+
+
+def _check(code, what):
+    if code != OK:
+        raise LbmrvError(code, what)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def lattice_tables(lattice):
+    """Integer directions c [q, 3] and weights w [q] as the library defines them."""
+    q, _ = QD[lattice]
+    c = (ctypes.c_int32 * (3 * q))()
+    w = (_c_double * q)()
+    _check(library().lbmrv_lattice_tables(LATTICES[lattice], c, w), "lbmrv_lattice_tables")
+    return np.array(c[:], dtype=np.int64).reshape(q, 3), np.array(w[:])
+
+
+class Lbmrv:
+    """One context: lattice, basis, lambda, rates, grid (nx, ny[, nz]) and storage."""
+
+    def __init__(self, lattice, s, dims, storage="f32", basis="default", lam=1.0, rho0=1.0):
+        self.lattice, self.basis, self.storage = lattice, basis, storage
+        self.q, self.d = QD[lattice]
+        self.dims = tuple(int(x) for x in dims)
+        if len(self.dims) != self.d:
+            raise ValueError("dims must have %d entries" % self.d)
+        self.lam = float(lam)
+        self.rho0 = float(rho0)
+        rates = (_c_double * self.q)(*[float(x) for x in s])
+        dd = (_c_int64 * 3)(*(list(self.dims) + [1] * (3 - self.d)))
+        h = _c_void_p()
+        _check(library().lbmrv_create(ctypes.byref(h), LATTICES[lattice], BASES[basis], self.lam, rates, dd,
+                                      STORAGES[storage], self.rho0), "lbmrv_create")
+        self._h = h
+        self.N = int(np.prod(self.dims))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            library().lbmrv_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # shapes and dtypes
+    @property
+    def grid_shape(self):
+        """Array shape of one population field: (ny, nx) or (nz, ny, nx)."""
+        return tuple(reversed(self.dims))
+
+    @property
+    def torch_dtype(self):
+        import torch
+        return {"f64": torch.float64, "f32": torch.float32, "f32dev": torch.float32,
+                "f16dev": torch.float16}[self.storage]
+
+    @property
+    def out_dtype(self):
+        import torch
+        return torch.float64 if self.storage == "f64" else torch.float32
+
+    def empty(self, device="cuda"):
+        import torch
+        return torch.empty((self.q,) + self.grid_shape, dtype=self.torch_dtype, device=device)
+
+    # calls
+    def set_rates(self, s):
+        rates = (_c_double * self.q)(*[float(x) for x in s])
+        _check(library().lbmrv_set_rates(self._h, rates), "lbmrv_set_rates")
+
+    def set_streaming(self, kind):
+        _check(library().lbmrv_set_streaming(self._h, STREAMING[kind]), "lbmrv_set_streaming")
+
+    def step(self, f_in, f_out, mode="zero", alpha=1.0, field=None, nsteps=1, stream=None):
+        _check(library().lbmrv_step(self._h, _ptr(f_in), _ptr(f_out), MODES[mode], float(alpha), _ptr(field),
+                                    int(nsteps), _stream(stream)), "lbmrv_step")
+
+    def collide(self, f_in, f_out, mode="zero", alpha=1.0, field=None, stream=None):
+        _check(library().lbmrv_collide(self._h, _ptr(f_in), _ptr(f_out), MODES[mode], float(alpha), _ptr(field),
+                                       _stream(stream)), "lbmrv_collide")
+
+    def transport(self, f_in, f_out, stream=None):
+        _check(library().lbmrv_transport(self._h, _ptr(f_in), _ptr(f_out), _stream(stream)), "lbmrv_transport")
+
+    def moments(self, f, with_m0=False, stream=None):
+        import torch
+        rho = torch.empty(self.grid_shape, dtype=self.out_dtype, device=f.device)
+        u = torch.empty((self.d,) + self.grid_shape, dtype=self.out_dtype, device=f.device)
+        m0 = torch.empty((self.q,) + self.grid_shape, dtype=self.out_dtype, device=f.device) if with_m0 else None
+        _check(library().lbmrv_moments(self._h, _ptr(f), _ptr(rho), _ptr(u), _ptr(m0), _stream(stream)),
+               "lbmrv_moments")
+        return rho, u, m0
+
+    def conservation(self, f, stream=None):
+        """(mass, momentum[d]) in FP64 and whether every population is finite."""
+        out = (_c_double * 4)()
+        rc = library().lbmrv_conservation(self._h, _ptr(f), out, _stream(stream))
+        if rc not in (OK, ERR_NONFINITE):
+            _check(rc, "lbmrv_conservation")
+        return out[0], list(out[1:1 + self.d]), rc == OK
+
+    def init_equilibrium(self, rho, u, noise=None, amp=0.0, out=None, stream=None):
+        out = self.empty(rho.device) if out is None else out
+        _check(library().lbmrv_init_equilibrium(self._h, _ptr(rho), _ptr(u), _ptr(noise), float(amp), _ptr(out),
+                                                _stream(stream)), "lbmrv_init_equilibrium")
+        return out
+
+    def import_f64(self, f, out=None, stream=None):
+        out = self.empty(f.device) if out is None else out
+        _check(library().lbmrv_import(self._h, _ptr(f), _ptr(out), _stream(stream)), "lbmrv_import")
+        return out
+
+    def export_f64(self, f, out=None, stream=None):
+        import torch
+        out = torch.empty((self.q,) + self.grid_shape, dtype=torch.float64, device=f.device) if out is None else out
+        _check(library().lbmrv_export(self._h, _ptr(f), _ptr(out), _stream(stream)), "lbmrv_export")
+        return out

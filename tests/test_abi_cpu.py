@@ -1,0 +1,128 @@
+"""The C-ABI library loads, exports every declared symbol, and validates its
+arguments on the host (no GPU needed: validation precedes any HIP call)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1312_3297_amd import lbmrv
+from oracle import lattices
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbmrv.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    return re.findall(r"^\s*(?:int|void|const char \*|size_t)\s*\**\s*(lbmrv_\w+)\s*\(", src, re.M)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = lbmrv.library()
+    names = declared_functions()
+    assert len(names) >= 12
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_signatures_cover_header():
+    assert set(declared_functions()) == set(lbmrv._SIGS)
+
+
+@pytest.mark.parametrize("name,lat", [("d2q9", "d2q9"), ("d3q19", "d3q19"), ("d3q27", "d3q27")])
+def test_lattice_tables_match_documented_order(name, lat):
+    """The library's directions and weights are the interface order; the oracle
+    writes the same convention independently."""
+    c, w = lbmrv.lattice_tables(name)
+    ol = lattices.make(lat)
+    assert np.array_equal(c, ol.c)
+    assert np.array_equal(w, ol.w)
+
+
+GOOD9 = [0, 0, 0, 1.4, 1.7, 1.7, 1.2, 1.2, 1.4]
+
+
+@pytest.mark.parametrize("kw,err", [
+    (dict(s=[0, 0, 0.1, 1, 1, 1, 1, 1, 1]), lbmrv.ERR_INVALID_ARG),      # rate on a conserved moment
+    (dict(s=[0, 0, 0, 2.5, 1, 1, 1, 1, 1]), lbmrv.ERR_INVALID_ARG),      # rate outside [0, 2]
+    (dict(s=[0, 0, 0, float("nan"), 1, 1, 1, 1, 1]), lbmrv.ERR_INVALID_ARG),
+    (dict(lam=0.0), lbmrv.ERR_INVALID_ARG),
+    (dict(lam=-1.0), lbmrv.ERR_INVALID_ARG),
+    (dict(dims=(0, 8)), lbmrv.ERR_INVALID_ARG),
+    (dict(dims=(8, 70000)), lbmrv.ERR_INVALID_ARG),
+    (dict(rho0=float("inf")), lbmrv.ERR_INVALID_ARG),
+])
+def test_create_rejects_invalid_arguments(kw, err):
+    args = dict(lattice="d2q9", s=GOOD9, dims=(8, 8), storage="f32", basis="default", lam=1.0, rho0=1.0)
+    args.update(kw)
+    with pytest.raises(lbmrv.LbmrvError) as e:
+        lbmrv.Lbmrv(**args)
+    assert e.value.code == err
+
+
+def test_create_rejects_geier_basis_in_3d():
+    with pytest.raises(lbmrv.LbmrvError):
+        lbmrv.Lbmrv("d3q19", [0.0] * 4 + [1.0] * 15, (4, 4, 4), basis="geier")
+
+
+def test_create_rejects_too_many_nodes():
+    with pytest.raises(lbmrv.LbmrvError):
+        lbmrv.Lbmrv("d3q27", [0.0] * 4 + [1.0] * 23, (4096, 4096, 16))
+
+
+class _Fake:
+    """Stands in for a device tensor: only data_ptr() is used by the binding."""
+
+    def __init__(self, p):
+        self.p = p
+
+    def data_ptr(self):
+        return self.p
+
+
+def test_step_validation_happens_before_any_hip_call():
+    ctx = lbmrv.Lbmrv("d2q9", GOOD9, (8, 8), storage="f32")
+    lib = lbmrv.library()
+    a, b = ctypes.c_void_p(4096), ctypes.c_void_p(8192)
+    st = ctypes.c_void_p(0)
+    # same buffer in and out
+    assert lib.lbmrv_step(ctx._h, a, a, 0, 1.0, None, 1, st) == lbmrv.ERR_INVALID_ARG
+    # null pointers
+    assert lib.lbmrv_step(ctx._h, None, b, 0, 1.0, None, 1, st) == lbmrv.ERR_INVALID_ARG
+    # misaligned population pointer
+    assert lib.lbmrv_step(ctx._h, ctypes.c_void_p(4098), b, 0, 1.0, None, 1, st) == lbmrv.ERR_ALIGNMENT
+    # FIELD mode without a field, unknown mode, negative steps, non-finite alpha
+    assert lib.lbmrv_step(ctx._h, a, b, 2, 1.0, None, 1, st) == lbmrv.ERR_INVALID_ARG
+    assert lib.lbmrv_step(ctx._h, a, b, 7, 1.0, None, 1, st) == lbmrv.ERR_INVALID_ARG
+    assert lib.lbmrv_step(ctx._h, a, b, 0, 1.0, None, -1, st) == lbmrv.ERR_INVALID_ARG
+    assert lib.lbmrv_step(ctx._h, a, b, 1, float("inf"), None, 1, st) == lbmrv.ERR_INVALID_ARG
+    assert lib.lbmrv_step(None, a, b, 0, 1.0, None, 1, st) == lbmrv.ERR_INVALID_ARG
+    assert lib.lbmrv_transport(ctx._h, a, a, st) == lbmrv.ERR_INVALID_ARG
+    assert lib.lbmrv_moments(ctx._h, a, None, b, None, st) == lbmrv.ERR_INVALID_ARG
+    assert lib.lbmrv_conservation(ctx._h, a, None, st) == lbmrv.ERR_INVALID_ARG
+    assert lib.lbmrv_set_streaming(ctx._h, 5) == lbmrv.ERR_INVALID_ARG
+    bad = (ctypes.c_double * 9)(*[0, 0, 0, 1, 1, 1, 1, 1, 3.0])
+    assert lib.lbmrv_set_rates(ctx._h, bad) == lbmrv.ERR_INVALID_ARG
+
+
+def test_f16_storage_needs_two_byte_alignment_only():
+    ctx = lbmrv.Lbmrv("d2q9", GOOD9, (8, 8), storage="f16dev")
+    lib = lbmrv.library()
+    st = ctypes.c_void_p(0)
+    assert lib.lbmrv_step(ctx._h, ctypes.c_void_p(4097), ctypes.c_void_p(8192), 0, 1.0, None, 1, st) \
+        == lbmrv.ERR_ALIGNMENT
+
+
+def test_info_reports_sizes():
+    ctx = lbmrv.Lbmrv("d3q19", [0.0] * 4 + [1.0] * 15, (5, 6, 7), storage="f16dev")
+    q, d, n, b = (ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64())
+    assert lbmrv.library().lbmrv_info(ctx._h, ctypes.byref(q), ctypes.byref(d), ctypes.byref(n), ctypes.byref(b)) == 0
+    assert (q.value, d.value, n.value, b.value) == (19, 3, 210, 2)
+
+
+def test_strerror_names_every_code():
+    lib = lbmrv.library()
+    for code in (0, -1, -2, -4, -5, -6):
+        assert lib.lbmrv_strerror(code).decode() != "unknown error code"

@@ -344,3 +344,21 @@ def test_shear_wave_viscosity(name, mode):
     nu = _shear_decay_rate(lat, s, mode, L=32, steps=300)
     nu_th = (1 / s_nu - 0.5) / 3
     assert abs(nu / nu_th - 1) < 5e-3, (nu, nu_th)
+
+
+def test_fp64_floor_between_two_oracles_on_the_64_shear_wave():
+    """The oracle's LU form and the separately written MRT form agree to 1e-13 on
+    f but only to ~1e-11 on u after 500 steps of the 64 x 64 shear wave: this is
+    the FP64 rounding floor that the GPU parity gate on u is set against."""
+    from paper_1312_3297_amd import workloads
+    lat = lattices.make("d2q9")
+    rho, u = workloads.shear_wave(64, 0.01)
+    f0 = A.equilibrium(lat, rho, u) + 1e-4 * workloads.noise(9, (64, 64), 1312)
+    a = A.run(lat, f0, S_GROUPED, 500)
+    c = f0
+    for _ in range(500):
+        c = mrt.mrt_step(c, S_GROUPED)
+    ua, uc = A.conserved(lat, a)[1], A.conserved(lat, c)[1]
+    assert np.abs(a - c).max() / np.abs(c).max() <= 1e-13
+    ru = np.abs(ua - uc).max() / np.abs(uc).max()
+    assert 1e-13 < ru <= 1e-11

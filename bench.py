@@ -101,6 +101,42 @@ def cpu_baseline(name, budget_s=15.0):
                                                                        steps, el)}
 
 
+def adjoint_cost(torch, L=512, nsteps=2000, K=100, reps=2):
+    """Cost of the discrete adjoint (forward with snapshots + recompute + reverse
+    sweep, FP64 accumulation of dJ/ds and dJ/du~) over the plain forward, on the
+    D2Q9 random-phase workload (amplitude 0.02, wavenumbers 1..8), FP32 storage,
+    u~ = u(x, 0) frozen."""
+    from paper_1312_3297_amd import workloads as W
+    from paper_1312_3297_amd.lbmrv import Lbmrv
+    s = W.RATES_D2Q9_GROUPED
+    ctx = Lbmrv("d2q9", s, (L, L), "f32")
+    ctx.set_streaming("push")
+    rho, u = W.random_phase(L, 0.02, 1, 8, 1315)
+    f0 = ctx.init_equilibrium(torch.from_numpy(rho).to("cuda"), torch.from_numpy(u).to("cuda"))
+    field = torch.from_numpy(u).to("cuda").to(torch.float32)
+    a, b = f0.clone(), torch.empty_like(f0)
+    cot = torch.randn((9, L, L), device="cuda", dtype=torch.float32)
+    ws = torch.empty(ctx.adjoint_workspace_bytes(nsteps, K), dtype=torch.uint8, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    fwd, adj = [], []
+    ctx.step(a, b, "field", 1.0, field, 10)
+    ctx.adjoint(f0, cot, 20, 7, "field", field, workspace=ws)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        a.copy_(f0)
+        ev[0].record()
+        ctx.step(a, b, "field", 1.0, field, nsteps)
+        ev[1].record()
+        ctx.adjoint(f0, cot, nsteps, K, "field", field, workspace=ws)
+        ev[2].record()
+        torch.cuda.synchronize()
+        fwd.append(ev[0].elapsed_time(ev[1]))
+        adj.append(ev[1].elapsed_time(ev[2]))
+    f_ms, a_ms = min(fwd), min(adj)
+    return {"workload": "d2q9_randomphase%d_f32_field" % L, "nsteps": nsteps, "K": K,
+            "forward_ms": round(f_ms, 3), "adjoint_ms": round(a_ms, 3), "cost_ratio": round(a_ms / f_ms, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +145,7 @@ def main():
     ap.add_argument("--workload", default="d3q19_tgv256_f32_fluid", choices=sorted(WORKLOADS))
     ap.add_argument("--streaming", default="pull", choices=["pull", "push"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--traffic-gb", type=float, default=None,
                     help="HBM bytes per launch of the dominant kernel from rocprofv3 counters (GB)")
@@ -180,6 +217,8 @@ def main():
         "state_finite": bool(finite),
         "wall_s": round(wall, 4),
     }
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_cost(torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(name, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -1,0 +1,284 @@
+// Adjoint of one time step (relaxation in the moving frame, then transport),
+// for a relative velocity that does not depend on f (zero or a given field).
+//
+// Forward step at node x (scatter form, pre-collision states):
+//   f^{n+1}_j(x + c_j) = f*_j(x),
+//   f* = f + M_W^{-1} T(-u~) R^{-1} S R T(u~) d0,   d0 = m^eq_W(rho, u) - M_W f
+// (eq. (relaxationu) written on increments, T(u~) = prod_a exp(-u~_a D_a)).
+// With g_j = lambda^{n+1}_j(x + c_j) (the transpose of the transport), the
+// transpose of the collision Jacobian is, with the working vectors
+//   z1 = M_W^{-T} g,  z2 = T(-u~)^T z1,  z3 = R^{-T} z2,  z5 = R^T S z3,
+//   z6 = T(u~)^T z5,  y = M_W^T z6:
+//   lambda^n_i = g_i - y_i + dm^eq/dh_i . z6
+//   dJ/ds_k   += z3_k (R T(u~) d0)_k
+//   dJ/du~_a  += z2 . D_a (R^{-1} S R v) - z5 . D_a v,   v = T(u~) d0
+// using d/du~_a T(u~) = -D_a T(u~) and that the D_a commute with T.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace lbmrv {
+
+template <class T>
+struct AdjArgs {
+  const void* f;       // f^n, storage type, [q][N]
+  const T* lam_in;     // lambda^{n+1} [q][N]
+  T* lam_out;          // lambda^n [q][N]
+  const float* ut;     // [d][N] u~ field in physical units (FIELD) or null
+  double* grad_ut;     // [d][N] FP64 accumulators (FIELD) or null
+  double* partial;     // [nblocks][Q] FP64 accumulators of dJ/ds, one row per block
+  uint32_t nx, ny, nz;
+  uint64_t N;
+  T rho0, inv_lambda;
+  T s[27];
+};
+
+template <class B, int ST, int MODE>
+__global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> a) {
+  using L = typename B::Lat;
+  using S = typename Store<ST>::S;
+  using T = typename Store<ST>::T;
+  using Tb = Tab<B>;
+  constexpr int Q = B::Q;
+  constexpr int D = L::D;
+  static_assert(MODE != UT_FLUID, "the adjoint takes u~ independent of f");
+
+  const uint32_t xr = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = xr < a.nx;
+  const uint32_t x = active ? xr : a.nx - 1;  // inactive lanes recompute a valid node, store nothing
+  const uint32_t y = blockIdx.y, z = blockIdx.z;
+  const uint32_t nx = a.nx, ny = a.ny, nz = a.nz;
+  const uint32_t xp = x == nx - 1 ? 0 : x + 1, xm = x == 0 ? nx - 1 : x - 1;
+  const uint32_t yp = y == ny - 1 ? 0 : y + 1, ym = y == 0 ? ny - 1 : y - 1;
+  const uint32_t zp = z == nz - 1 ? 0 : z + 1, zm = z == 0 ? nz - 1 : z - 1;
+  const uint32_t own = (z * ny + y) * nx + x;
+  const uint64_t N = a.N;
+  const S* f = static_cast<const S*>(a.f);
+
+  T h[Q], g[Q];
+  sfor<Q>([&](auto jj) {
+    constexpr int J = jj;
+    constexpr int cx = L::c[J].x, cy = L::c[J].y, cz = L::c[J].z;
+    const uint32_t xx = cx == 0 ? x : (cx > 0 ? xp : xm);
+    const uint32_t yy = cy == 0 ? y : (cy > 0 ? yp : ym);
+    const uint32_t zz = cz == 0 ? z : (cz > 0 ? zp : zm);
+    h[J] = T(f[(uint64_t)J * N + own]);
+    g[J] = a.lam_in[(uint64_t)J * N + (zz * ny + yy) * nx + xx];
+  });
+
+  // ---- forward quantities at this node
+  T drho = h[0];
+  sfor<Q - 1>([&](auto jj) { drho += h[jj + 1]; });
+  T jm[3] = {T(0), T(0), T(0)};
+  sfor<Q>([&](auto jj) {
+    constexpr int J = jj;
+    if constexpr (L::c[J].x > 0) jm[0] += h[J];
+    if constexpr (L::c[J].x < 0) jm[0] -= h[J];
+    if constexpr (L::c[J].y > 0) jm[1] += h[J];
+    if constexpr (L::c[J].y < 0) jm[1] -= h[J];
+    if constexpr (L::c[J].z > 0) jm[2] += h[J];
+    if constexpr (L::c[J].z < 0) jm[2] -= h[J];
+  });
+  const T rho = a.rho0 + drho;
+  const T irho = T(1) / rho;
+  const T u[3] = {jm[0] * irho, jm[1] * irho, D == 3 ? jm[2] * irho : T(0)};
+  T ut[3] = {T(0), T(0), T(0)};
+  if constexpr (MODE == UT_FIELD) {
+    sfor<D>([&](auto al) { ut[al] = T(a.ut[(uint64_t)al * N + own]) * a.inv_lambda; });
+  }
+
+  T v[Q];  // d0, then T(u~) d0
+  sfor<Q>([&](auto kk) {
+    constexpr int K = kk;
+    if constexpr (K <= D) {
+      v[K] = T(0);
+    } else {
+      T mh = T(0);
+      sfor<Tb::t.sMW[K].n>([&](auto i) { axpy_c<Tb::t.sMW[K].val[i]>(mh, h[Tb::t.sMW[K].col[i]]); });
+      T quad = T(0);
+      sfor<D>([&](auto al) {
+        constexpr Rat bb = Tb::t.b[K][al];
+        if constexpr (!bb.zero()) quad = fmac(lit<bb, T>(), u[al], quad);
+        sfor<D>([&](auto be) {
+          if constexpr (be >= al) {
+            constexpr Rat cc = (be == al) ? Tb::t.C[K][al][be] : Tb::t.C[K][al][be] + Tb::t.C[K][be][al];
+            if constexpr (!cc.zero()) quad = fmac(lit<cc, T>() * u[al], u[be], quad);
+          }
+        });
+      });
+      T eq = rho * quad;
+      constexpr Rat ak = Tb::t.a[K];
+      if constexpr (!ak.zero()) eq = fmac(lit<ak, T>(), drho, eq);
+      v[K] = eq - mh;
+    }
+  });
+
+  // out = prod_a exp(sign u~_a D_a) in (rows: transposed or not), non-conserved block
+  auto apply_shift = [&](T (&w)[Q], T sign, auto transposed) {
+    constexpr bool TR = decltype(transposed)::value;
+    sfor<D>([&](auto ax) {
+      constexpr int AX = ax;
+      constexpr int NM = Tb::t.nmax[AX];
+      T pw[kP];
+      pw[1] = sign * ut[AX];
+      sfor<NM>([&](auto nn) {
+        if constexpr (nn + 1 >= 2) pw[nn + 1] = pw[nn] * pw[1];
+      });
+      T out[Q];
+      sfor<Q>([&](auto kk) {
+        constexpr int K = kk;
+        out[K] = w[K];
+        if constexpr (K > D) {
+          sfor<NM>([&](auto nn) {
+            constexpr int NN = nn + 1;
+            constexpr auto row = TR ? Tb::t.tE[AX][NN][K] : Tb::t.sE[AX][NN][K];
+            if constexpr (row.n > 0) {
+              T acc = T(0);
+              sfor<row.n>([&](auto i) { axpy_c<row.val[i]>(acc, w[row.col[i]]); });
+              out[K] = fmac(pw[NN], acc, out[K]);
+            }
+          });
+        }
+      });
+      sfor<Q>([&](auto kk) { w[kk] = out[kk]; });
+    });
+  };
+  if constexpr (MODE != UT_ZERO) apply_shift(v, T(-1), std::false_type{});
+
+  T r[Q], am[Q];  // r = R v (user basis), am = R^{-1} S r
+  sfor<Q>([&](auto kk) {
+    constexpr int K = kk;
+    T acc = T(0);
+    if constexpr (K > D) sfor<Tb::t.sR[K].n>([&](auto i) { axpy_c<Tb::t.sR[K].val[i]>(acc, v[Tb::t.sR[K].col[i]]); });
+    r[K] = acc;
+  });
+  sfor<Q>([&](auto kk) {
+    constexpr int K = kk;
+    T acc = T(0);
+    if constexpr (K > D)
+      sfor<Tb::t.sRinv[K].n>([&](auto i) {
+        constexpr int l = Tb::t.sRinv[K].col[i];
+        axpy_c<Tb::t.sRinv[K].val[i]>(acc, r[l] * a.s[l]);
+      });
+    am[K] = acc;
+  });
+
+  // ---- adjoint
+  T zz[Q];  // z1 -> z2 (in place through the shift)
+  sfor<Q>([&](auto kk) {
+    constexpr int K = kk;
+    T acc = T(0);
+    if constexpr (K > D)
+      sfor<Tb::t.tMWinv[K].n>([&](auto i) { axpy_c<Tb::t.tMWinv[K].val[i]>(acc, g[Tb::t.tMWinv[K].col[i]]); });
+    zz[K] = acc;
+  });
+  if constexpr (MODE != UT_ZERO) apply_shift(zz, T(1), std::true_type{});  // z2 = T(-u~)^T z1
+
+  T z3[Q], z5[Q];
+  sfor<Q>([&](auto kk) {
+    constexpr int K = kk;
+    T acc = T(0);
+    if constexpr (K > D)
+      sfor<Tb::t.tRinv[K].n>([&](auto i) { axpy_c<Tb::t.tRinv[K].val[i]>(acc, zz[Tb::t.tRinv[K].col[i]]); });
+    z3[K] = acc;
+  });
+  sfor<Q>([&](auto kk) {
+    constexpr int K = kk;
+    T acc = T(0);
+    if constexpr (K > D)
+      sfor<Tb::t.tR[K].n>([&](auto i) {
+        constexpr int l = Tb::t.tR[K].col[i];
+        axpy_c<Tb::t.tR[K].val[i]>(acc, z3[l] * a.s[l]);
+      });
+    z5[K] = acc;
+  });
+
+  // dJ/du~ (FIELD): z2 . D_a am - z5 . D_a v, per node, in physical units
+  if constexpr (MODE == UT_FIELD) {
+    if (active) {
+      sfor<D>([&](auto ax) {
+        constexpr int AX = ax;
+        T gsum = T(0);
+        sfor<Q>([&](auto kk) {
+          constexpr int K = kk;
+          constexpr auto row = Tb::t.sE[AX][1][K];
+          if constexpr (K > D && row.n > 0) {
+            T da = T(0), dv = T(0);
+            sfor<row.n>([&](auto i) {
+              axpy_c<row.val[i]>(da, am[row.col[i]]);
+              axpy_c<row.val[i]>(dv, v[row.col[i]]);
+            });
+            gsum = fmac(zz[K], da, gsum);
+            gsum = fmac(-z5[K], dv, gsum);
+          }
+        });
+        a.grad_ut[(uint64_t)AX * N + own] += double(gsum * a.inv_lambda);
+      });
+    }
+  }
+
+  // z6 = T(u~)^T z5
+  if constexpr (MODE != UT_ZERO) apply_shift(z5, T(-1), std::true_type{});
+
+  // lambda^n = g - M_W^T z6 + (d m^eq / d h)^T z6
+  T A0 = T(0), Bv[3] = {T(0), T(0), T(0)};
+  sfor<Q>([&](auto kk) {
+    constexpr int K = kk;
+    if constexpr (K > D) {
+      T quad = T(0);
+      sfor<D>([&](auto al) {
+        constexpr Rat bb = Tb::t.b[K][al];
+        T dq = T(0);
+        if constexpr (!bb.zero()) {
+          quad = fmac(lit<bb, T>(), u[al], quad);
+          dq = lit<bb, T>();
+        }
+        sfor<D>([&](auto be) {
+          constexpr Rat cab = Tb::t.C[K][al][be];
+          constexpr Rat csym = Tb::t.C[K][al][be] + Tb::t.C[K][be][al];
+          if constexpr (!cab.zero()) quad = fmac(lit<cab, T>() * u[al], u[be], quad);
+          if constexpr (!csym.zero()) dq = fmac(lit<csym, T>(), u[be], dq);
+        });
+        Bv[al] = fmac(z5[K], dq, Bv[al]);
+      });
+      constexpr Rat ak = Tb::t.a[K];
+      A0 = fmac(z5[K], lit<ak, T>() + quad, A0);
+    }
+  });
+  if (active) {
+    T* lo = a.lam_out;
+    sfor<Q>([&](auto jj) {
+      constexpr int J = jj;
+      T yv = T(0);
+      sfor<Tb::t.tMW[J].n>([&](auto i) { axpy_c<Tb::t.tMW[J].val[i]>(yv, z5[Tb::t.tMW[J].col[i]]); });
+      T lam = g[J] - yv + A0;
+      sfor<D>([&](auto al) {
+        constexpr int cj = al == 0 ? L::c[J].x : al == 1 ? L::c[J].y : L::c[J].z;
+        lam = fmac(Bv[al], T(cj) - u[al], lam);
+      });
+      lo[(uint64_t)J * N + own] = lam;
+    });
+  }
+
+  // dJ/ds_k: block sum of z3_k r_k in FP64, added to this block's row
+  __shared__ double red[4][Q];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  sfor<Q>([&](auto kk) {
+    constexpr int K = kk;
+    if constexpr (K > D) {
+      double c = active ? double(z3[K]) * double(r[K]) : 0.0;
+      for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+      if (lane == 0) red[wave][K] = c;
+    }
+  });
+  __syncthreads();
+  if (threadIdx.x < Q && (int)threadIdx.x > D) {
+    double sum = 0.0;
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int w = 0; w < nw; ++w) sum += red[w][threadIdx.x];
+    a.partial[(uint64_t)bid * Q + threadIdx.x] += sum;
+  }
+}
+
+}  // namespace lbmrv

@@ -29,9 +29,27 @@ __global__ __launch_bounds__(kRedThreads) void k_conserve_final(const double* pa
   if (threadIdx.x < 5) out[threadIdx.x] = red[threadIdx.x][0];
 }
 
+__global__ __launch_bounds__(256) void k_fill_zero(double* p, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+// grad_s[k] = sum over blocks of partial[b][k] in block order (deterministic);
+// zero for the conserved moments k <= d.
+__global__ __launch_bounds__(64) void k_reduce_columns(const double* partial, uint64_t nblocks, int q, int d,
+                                                       double* out) {
+  const int k = threadIdx.x;
+  if (k >= q) return;
+  double s = 0.0;
+  if (k > d)
+    for (uint64_t b = 0; b < nblocks; ++b) s += partial[b * q + k];
+  out[k] = s;
+}
+
 namespace {
 
 using StepFn = hipError_t (*)(const StepLaunch&);
+using AdjFn = hipError_t (*)(const AdjLaunch&);
 using MomFn = hipError_t (*)(const MomLaunch&);
 using ConsFn = hipError_t (*)(const void*, uint64_t, double*, hipStream_t);
 using InitFn = hipError_t (*)(const InitLaunch&);
@@ -43,6 +61,7 @@ struct Entry {
   ConsFn cons[3];
   InitFn init[3];
   ConvFn conv[3];
+  AdjFn adj[3];
 };
 
 #define LBMRV_ENTRY(NAME)                                                                 \
@@ -51,7 +70,8 @@ struct Entry {
         {launch_moments_##NAME##_f64, launch_moments_##NAME##_f32, launch_moments_##NAME##_f16}, \
         {launch_conserve_##NAME##_f64, launch_conserve_##NAME##_f32, launch_conserve_##NAME##_f16}, \
         {launch_init_##NAME##_f64, launch_init_##NAME##_f32, launch_init_##NAME##_f16},   \
-        {launch_convert_##NAME##_f64, launch_convert_##NAME##_f32, launch_convert_##NAME##_f16} \
+        {launch_convert_##NAME##_f64, launch_convert_##NAME##_f32, launch_convert_##NAME##_f16}, \
+        {launch_adjoint_##NAME##_f64, launch_adjoint_##NAME##_f32, launch_adjoint_##NAME##_f16} \
   }
 
 const Entry kEntries[4] = {LBMRV_ENTRY(d2q9_paper), LBMRV_ENTRY(d2q9_geier), LBMRV_ENTRY(d3q19),
@@ -389,6 +409,126 @@ int lbmrv_lattice_tables(int lattice, int32_t* cdirs, double* w) {
   else if (lattice == LBMRV_D3Q19) fill(D3Q19Lat{});
   else fill(D3Q27Lat{});
   return LBMRV_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct AdjPlan {
+  int64_t nseg, nsnap, nsegslots;
+  size_t state_bytes, lam_bytes, partial_bytes, total;
+  uint64_t nblocks;
+};
+
+AdjPlan adj_plan(const lbmrv_ctx* c, int64_t nsteps, int64_t K) {
+  AdjPlan p{};
+  p.nseg = (nsteps + K - 1) / K;
+  p.nsnap = p.nseg - 1;
+  p.nsegslots = (nsteps < K ? nsteps : K) - 1;
+  p.state_bytes = align256(elem_bytes(c->storage) * c->q * c->N);
+  p.lam_bytes = align256((c->storage == LBMRV_F64 ? 8 : 4) * (size_t)c->q * c->N);
+  const uint64_t gx = (c->nx + c->block - 1) / c->block;
+  p.nblocks = gx * c->ny * c->nz;
+  p.partial_bytes = align256(sizeof(double) * p.nblocks * c->q);
+  p.total = p.state_bytes * (size_t)(p.nsnap + p.nsegslots + 1) + 2 * p.lam_bytes + p.partial_bytes;
+  return p;
+}
+
+hipError_t fill_zero(double* p, uint64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbmrv_adjoint_workspace_bytes(const lbmrv_ctx* c, int64_t nsteps, int64_t K) {
+  if (!c || nsteps < 1 || K < 1) return 0;
+  return adj_plan(c, nsteps, K).total;
+}
+
+int lbmrv_adjoint(lbmrv_ctx* c, const void* f0, int ut_mode, const float* ut_field, int64_t nsteps, int64_t K,
+                  const void* cot_fN, void* workspace, size_t workspace_bytes, void* f_N, void* grad_f0,
+                  double* grad_s, double* grad_ut, void* hip_stream) {
+  if (!c) return LBMRV_ERR_INVALID_ARG;
+  if (ut_mode == LBMRV_UT_FLUID) return LBMRV_ERR_UNSUPPORTED;  // u~ must not depend on f
+  if (ut_mode != LBMRV_UT_ZERO && ut_mode != LBMRV_UT_FIELD) return LBMRV_ERR_INVALID_ARG;
+  if (nsteps < 1 || K < 1) return LBMRV_ERR_INVALID_ARG;
+  const size_t eb = elem_bytes(c->storage);
+  const size_t tb = c->storage == LBMRV_F64 ? 8 : 4;
+  int rc;
+  if ((rc = check_ptr(f0, eb)) || (rc = check_ptr(cot_fN, tb)) || (rc = check_ptr(workspace, 256)) ||
+      (rc = check_ptr(grad_f0, tb)) || (rc = check_ptr(grad_s, 8)))
+    return rc;
+  if (f_N && (rc = check_ptr(f_N, eb))) return rc;
+  if (ut_mode == LBMRV_UT_FIELD && ((rc = check_ptr(ut_field, 4)) || (rc = check_ptr(grad_ut, 8)))) return rc;
+  const AdjPlan P = adj_plan(c, nsteps, K);
+  if (workspace_bytes < P.total) return LBMRV_ERR_INVALID_ARG;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+
+  char* w = static_cast<char*>(workspace);
+  char* snaps = w;
+  char* segs = snaps + P.state_bytes * P.nsnap;
+  char* fscratch = segs + P.state_bytes * P.nsegslots;
+  char* lam0 = fscratch + P.state_bytes;
+  char* lam1 = lam0 + P.lam_bytes;
+  double* partial = reinterpret_cast<double*>(lam1 + P.lam_bytes);
+  void* fN = f_N ? f_N : fscratch;
+  auto state = [&](int64_t t) -> void* {
+    if (t == 0) return const_cast<void*>(f0);
+    if (t == nsteps) return fN;
+    if (t % K == 0) return snaps + P.state_bytes * (t / K - 1);
+    return segs + P.state_bytes * (t % K - 1);
+  };
+  const Entry& E = kEntries[c->entry];
+  hipError_t e;
+  // forward sweep (scatter form, pre-collision states), keeping every K-th state
+  for (int64_t t = 0; t < nsteps; ++t) {
+    e = run_kind(c, K_PUSH, state(t), state(t + 1), ut_mode, 0.0, ut_field, st);
+    if (e != hipSuccess) return LBMRV_ERR_HIP;
+  }
+  if ((e = fill_zero(partial, P.nblocks * c->q, st)) != hipSuccess) return LBMRV_ERR_HIP;
+  if (ut_mode == LBMRV_UT_FIELD && (e = fill_zero(grad_ut, (uint64_t)c->d * c->N, st)) != hipSuccess)
+    return LBMRV_ERR_HIP;
+  AdjLaunch A{};
+  A.mode = ut_mode;
+  A.ut = ut_field;
+  A.grad_ut = ut_mode == LBMRV_UT_FIELD ? grad_ut : nullptr;
+  A.partial = partial;
+  A.nx = c->nx;
+  A.ny = c->ny;
+  A.nz = c->nz;
+  A.N = c->N;
+  A.rho0 = c->rho0;
+  A.inv_lambda = 1.0 / c->lambda;
+  for (int k = 0; k < 27; ++k) A.s[k] = k < c->q ? c->s[k] : 0.0;
+  A.stream = st;
+  A.block = c->block;
+  // reverse sweep, one segment of K steps at a time; the last segment's states
+  // are still in place from the forward sweep, earlier ones are recomputed
+  for (int64_t sg = P.nseg - 1; sg >= 0; --sg) {
+    const int64_t t0 = sg * K;
+    const int64_t t1 = (t0 + K < nsteps) ? t0 + K : nsteps;
+    if (sg < P.nseg - 1) {
+      for (int64_t t = t0; t + 1 < t1; ++t) {
+        e = run_kind(c, K_PUSH, state(t), state(t + 1), ut_mode, 0.0, ut_field, st);
+        if (e != hipSuccess) return LBMRV_ERR_HIP;
+      }
+    }
+    for (int64_t t = t1 - 1; t >= t0; --t) {
+      A.f = state(t);
+      A.lam_in = (t == nsteps - 1) ? cot_fN : ((t + 1) % 2 ? lam1 : lam0);
+      A.lam_out = (t == 0) ? grad_f0 : (t % 2 ? lam1 : lam0);
+      if ((e = E.adj[c->sk](A)) != hipSuccess) return LBMRV_ERR_HIP;
+    }
+  }
+  hipLaunchKernelGGL(k_reduce_columns, dim3(1), dim3(64), 0, st, partial, P.nblocks, c->q, c->d, grad_s);
+  return hipGetLastError() == hipSuccess ? LBMRV_OK : LBMRV_ERR_HIP;
 }
 
 void lbmrv_destroy(lbmrv_ctx* c) {

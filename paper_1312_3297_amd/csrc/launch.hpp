@@ -6,6 +6,7 @@
 
 #include <cstdint>
 
+#include "adjoint.hpp"
 #include "kernels.hpp"
 
 namespace lbmrv {
@@ -127,6 +128,52 @@ hipError_t launch_convert_t(const void* in, void* out, double rho0, uint64_t N, 
   return hipGetLastError();
 }
 
+struct AdjLaunch {
+  int mode;  // UT_ZERO or UT_FIELD
+  const void* f;
+  const void* lam_in;
+  void* lam_out;
+  const float* ut;
+  double* grad_ut;
+  double* partial;
+  uint32_t nx, ny, nz;
+  uint64_t N;
+  double rho0, inv_lambda;
+  double s[27];
+  hipStream_t stream;
+  int block;
+};
+
+template <class B, int ST, int MODE>
+hipError_t launch_adjoint_t(const AdjLaunch& L) {
+  using T = typename Store<ST>::T;
+  AdjArgs<T> a{};
+  a.f = L.f;
+  a.lam_in = static_cast<const T*>(L.lam_in);
+  a.lam_out = static_cast<T*>(L.lam_out);
+  a.ut = L.ut;
+  a.grad_ut = L.grad_ut;
+  a.partial = L.partial;
+  a.nx = L.nx;
+  a.ny = L.ny;
+  a.nz = L.nz;
+  a.N = L.N;
+  a.rho0 = T(L.rho0);
+  a.inv_lambda = T(L.inv_lambda);
+  for (int k = 0; k < 27; ++k) a.s[k] = T(L.s[k]);
+  const int bx = L.block;
+  dim3 grid((L.nx + bx - 1) / bx, L.ny, L.nz);
+  hipLaunchKernelGGL((k_adjoint<B, ST, MODE>), grid, dim3(bx), 0, L.stream, a);
+  return hipGetLastError();
+}
+
+template <class B, int ST>
+hipError_t launch_adjoint_s(const AdjLaunch& L) {
+  if (L.mode == UT_ZERO) return launch_adjoint_t<B, ST, UT_ZERO>(L);
+  if (L.mode == UT_FIELD) return launch_adjoint_t<B, ST, UT_FIELD>(L);
+  return hipErrorInvalidValue;
+}
+
 // Per-(lattice, basis, storage) entry points, defined in the lattice translation
 // units (one unit per lattice and storage type, so they compile in parallel).
 #define LBMRV_DECLARE_LAUNCHERS(NAME, SKN)                                                  \
@@ -135,6 +182,7 @@ hipError_t launch_convert_t(const void* in, void* out, double rho0, uint64_t N, 
   hipError_t launch_conserve_##NAME##_##SKN(const void* f, uint64_t N, double* partial,     \
                                             hipStream_t st);                                \
   hipError_t launch_init_##NAME##_##SKN(const InitLaunch& L);                               \
+  hipError_t launch_adjoint_##NAME##_##SKN(const AdjLaunch& L);                             \
   hipError_t launch_convert_##NAME##_##SKN(const void* in, void* out, double rho0, uint64_t N, \
                                            int to_storage, hipStream_t st);
 
@@ -148,6 +196,7 @@ hipError_t launch_convert_t(const void* in, void* out, double rho0, uint64_t N, 
     return launch_conserve_partial<BASIS, ST>(f, N, partial, st);                           \
   }                                                                                         \
   hipError_t launch_init_##NAME##_##SKN(const InitLaunch& L) { return launch_init_t<BASIS, ST>(L); } \
+  hipError_t launch_adjoint_##NAME##_##SKN(const AdjLaunch& L) { return launch_adjoint_s<BASIS, ST>(L); } \
   hipError_t launch_convert_##NAME##_##SKN(const void* in, void* out, double rho0, uint64_t N, \
                                            int to_storage, hipStream_t st) {               \
     return launch_convert_t<BASIS, ST>(in, out, rho0, N, to_storage, st);                   \

@@ -185,6 +185,13 @@ constexpr Mat<Q> mscale(const Mat<Q>& A, Rat s) {
   return C;
 }
 template <int Q>
+constexpr Mat<Q> mtrans(const Mat<Q>& A) {
+  Mat<Q> C;
+  for (int i = 0; i < Q; ++i)
+    for (int j = 0; j < Q; ++j) C.m[i][j] = A.m[j][i];
+  return C;
+}
+template <int Q>
 constexpr bool mzero(const Mat<Q>& A) {
   for (int i = 0; i < Q; ++i)
     for (int j = 0; j < Q; ++j)
@@ -401,6 +408,12 @@ struct Derived {
   SpRow<Q> sR[Q];         // R rows, non-conserved columns
   SpRow<Q> sRinv[Q];      // R^{-1} rows, non-conserved columns
   SpRow<Q> sE[3][kP][Q];  // D_a^n / n! rows, non-conserved columns
+  // transposed rows for the adjoint
+  SpRow<Q> tMWinv[Q];     // row k: (j, M_W^{-1}[j][k]), all j
+  SpRow<Q> tMW[Q];        // row j: (k, M_W[k][j]), non-conserved k
+  SpRow<Q> tR[Q];         // row l: (k, R[k][l]), non-conserved k
+  SpRow<Q> tRinv[Q];      // row l: (k, R^{-1}[k][l]), non-conserved k
+  SpRow<Q> tE[3][kP][Q];  // row l: (k, (D_a^n / n!)[k][l]), non-conserved k
   bool ok_rank, ok_closed, ok_R, ok_conserved, ok_lower, ok_hom;
 };
 
@@ -501,6 +514,20 @@ constexpr Derived<B::Q> derive() {
     t.sRinv[k] = sprow(t.Rinv, k, nc);
     for (int ax = 0; ax < 3; ++ax)
       for (int n = 1; n < kP; ++n) t.sE[ax][n][k] = sprow(t.E[ax][n], k, nc);
+  }
+  {
+    const Mat<Q> MWinvT = mtrans(t.MWinv), MWT = mtrans(t.MW), RT = mtrans(t.R), RinvT = mtrans(t.Rinv);
+    for (int k = 0; k < Q; ++k) {
+      t.tMWinv[k] = sprow(MWinvT, k, 0);
+      t.tMW[k] = sprow(MWT, k, nc);
+      t.tR[k] = sprow(RT, k, nc);
+      t.tRinv[k] = sprow(RinvT, k, nc);
+    }
+    for (int ax = 0; ax < 3; ++ax)
+      for (int n = 1; n < kP; ++n) {
+        const Mat<Q> ET = mtrans(t.E[ax][n]);
+        for (int k = 0; k < Q; ++k) t.tE[ax][n][k] = sprow(ET, k, nc);
+      }
   }
   t.ok_hom = true;
   for (int k = 0; k < Q; ++k) {

@@ -40,6 +40,9 @@ _SIGS = {
     "lbmrv_import": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p]),
     "lbmrv_export": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p]),
     "lbmrv_lattice_tables": (_c_int, [_c_int, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_c_double)]),
+    "lbmrv_adjoint_workspace_bytes": (ctypes.c_size_t, [_c_void_p, _c_int64, _c_int64]),
+    "lbmrv_adjoint": (_c_int, [_c_void_p, _c_void_p, _c_int, _c_void_p, _c_int64, _c_int64, _c_void_p, _c_void_p,
+                               ctypes.c_size_t, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
     "lbmrv_destroy": (None, [_c_void_p]),
     "lbmrv_strerror": (ctypes.c_char_p, [_c_int]),
 }
@@ -188,6 +191,32 @@ class Lbmrv:
                                                 _stream(stream)), "lbmrv_init_equilibrium")
         return out
 
+    @property
+    def compute_dtype(self):
+        import torch
+        return torch.float64 if self.storage == "f64" else torch.float32
+
+    def adjoint_workspace_bytes(self, nsteps, K):
+        return int(library().lbmrv_adjoint_workspace_bytes(self._h, int(nsteps), int(K)))
+
+    def adjoint(self, f0, cot_fN, nsteps, K=100, mode="zero", field=None, want_fN=False, workspace=None,
+                stream=None):
+        """Discrete adjoint of nsteps steps: (f_N or None, dJ/df0, dJ/ds [FP64], dJ/du~ [FP64] or None)."""
+        import torch
+        dev = f0.device
+        nbytes = self.adjoint_workspace_bytes(nsteps, K)
+        if workspace is None or workspace.numel() < nbytes:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        grad_f0 = torch.empty((self.q,) + self.grid_shape, dtype=self.compute_dtype, device=dev)
+        grad_s = torch.empty(self.q, dtype=torch.float64, device=dev)
+        grad_ut = torch.empty((self.d,) + self.grid_shape, dtype=torch.float64, device=dev) \
+            if mode == "field" else None
+        fN = self.empty(dev) if want_fN else None
+        _check(library().lbmrv_adjoint(self._h, _ptr(f0), MODES[mode], _ptr(field), int(nsteps), int(K),
+                                       _ptr(cot_fN), _ptr(workspace), nbytes, _ptr(fN), _ptr(grad_f0),
+                                       _ptr(grad_s), _ptr(grad_ut), _stream(stream)), "lbmrv_adjoint")
+        return fN, grad_f0, grad_s, grad_ut
+
     def import_f64(self, f, out=None, stream=None):
         out = self.empty(f.device) if out is None else out
         _check(library().lbmrv_import(self._h, _ptr(f), _ptr(out), _stream(stream)), "lbmrv_import")
@@ -198,3 +227,66 @@ class Lbmrv:
         out = torch.empty((self.q,) + self.grid_shape, dtype=torch.float64, device=f.device) if out is None else out
         _check(library().lbmrv_export(self._h, _ptr(f), _ptr(out), _stream(stream)), "lbmrv_export")
         return out
+
+
+# ---------------------------------------------------------------------------
+# autograd
+# ---------------------------------------------------------------------------
+def _steps_function():
+    import torch
+
+    class Steps(torch.autograd.Function):
+        """f_N = N steps of the scheme from f0 with rates s and relative velocity
+        field u~ (None: u~ = 0).  backward() runs the library's discrete adjoint
+        (lbmrv_adjoint) and returns dJ/df0, dJ/ds (FP64) and dJ/du~."""
+
+        @staticmethod
+        def forward(ctx, f0, s, field, lb, nsteps, K):
+            lb.set_rates([float(x) for x in s.detach().cpu()])
+            mode = "zero" if field is None else "field"
+            fin = f0.detach().clone()
+            fout = torch.empty_like(fin)
+            fld = None if field is None else field.detach().contiguous()
+            lb.step(fin, fout, mode, 1.0, fld, nsteps)
+            ctx.save_for_backward(f0, s, field if field is not None else torch.empty(0))
+            ctx.lb, ctx.nsteps, ctx.K, ctx.has_field = lb, nsteps, K, field is not None
+            return fout
+
+        @staticmethod
+        def backward(ctx, grad_fN):
+            f0, s, field = ctx.saved_tensors
+            lb = ctx.lb
+            lb.set_rates([float(x) for x in s.detach().cpu()])
+            mode = "field" if ctx.has_field else "zero"
+            cot = grad_fN.detach().to(lb.compute_dtype).contiguous()
+            fld = field.detach().contiguous() if ctx.has_field else None
+            _, gf, gs, gu = lb.adjoint(f0.detach().contiguous(), cot, ctx.nsteps, ctx.K, mode, fld)
+            g_field = gu.to(field.dtype) if ctx.has_field else None
+            return gf.to(f0.dtype), gs.to(device=s.device, dtype=s.dtype), g_field, None, None, None
+
+    return Steps
+
+
+_STEPS = None
+
+
+def steps(f0, s, field, lb, nsteps, K=100):
+    """Differentiable N-step map (see Steps)."""
+    global _STEPS
+    if _STEPS is None:
+        _STEPS = _steps_function()
+    return _STEPS.apply(f0, s, field, lb, nsteps, K)
+
+
+def kinetic_energy(lb, f):
+    """J = 1/2 sum_x |q|^2 / rho of a population tensor in the context's storage
+    (torch ops, differentiable): the objective of the adjoint workload."""
+    import torch
+    c, w = lattice_tables(lb.lattice)
+    ff = f.to(torch.float64)
+    if lb.storage in ("f32dev", "f16dev"):
+        ff = ff + torch.tensor(w * lb.rho0, dtype=torch.float64, device=f.device).reshape((-1,) + (1,) * lb.d)
+    rho = ff.sum(0)
+    v = torch.tensor(lb.lam * c[:, : lb.d], dtype=torch.float64, device=f.device)
+    qm = torch.einsum("ja,j...->a...", v, ff)
+    return 0.5 * ((qm * qm).sum(0) / rho).sum()

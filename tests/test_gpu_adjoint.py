@@ -1,0 +1,124 @@
+"""The HIP adjoint (lbmrv_adjoint, through the C ABI) against the FP64 adjoint
+oracle (Oracle E), and the autograd wrapper against it.
+
+Gates: FP64 storage 1e-10 normwise relative (both sides FP64, different
+operation order over tens of steps); FP32 forward with FP64 gradient
+accumulation 1e-4, the tolerance stated for the GPU adjoint against the FP64
+CPU adjoint.
+"""
+import numpy as np
+import pytest
+
+from oracle import adjoint as E
+from oracle import scheme as A
+from paper_1312_3297_amd import lbmrv, workloads
+from paper_1312_3297_amd.lbmrv import Lbmrv
+
+from _common import oracle_lattice, rel, to_storage
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def gpu(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    return t.to(dtype) if dtype is not None else t
+
+
+def _random_phase_state(lat, L, seed):
+    rho, u = workloads.random_phase(L, 0.02, 1, 8, seed)
+    return A.equilibrium(lat, rho, u), u
+
+
+@pytest.mark.parametrize("storage,nsteps,K,tol", [("f64", 37, 8, 1e-10), ("f32", 200, 100, 1e-4)])
+def test_adjoint_d2q9_random_phase_field(storage, nsteps, K, tol):
+    lat = oracle_lattice("d2q9")
+    L = 32
+    f0, u0 = _random_phase_state(lat, L, 1316)
+    st, f0w = to_storage(lat, f0, storage)
+    field = u0.astype(np.float32).astype(np.float64)          # u~ = u(x, 0), frozen
+    s = workloads.RATES_D2Q9_GROUPED
+    fN = A.run(lat, f0w, s, nsteps, mode=A.FIELD, field=field)
+    J, cot = E.kinetic_energy(lat, fN)
+    _, gf, gs, gu = E.vjp(lat, f0w, s, nsteps, cot, field=field, K=50)
+    ctx = Lbmrv("d2q9", s, (L, L), storage)
+    cdt = torch.float64 if storage == "f64" else torch.float32
+    fNg, gfg, gsg, gug = ctx.adjoint(gpu(st), gpu(cot, cdt), nsteps, K, "field",
+                                     gpu(field.astype(np.float32)), want_fN=True)
+    torch.cuda.synchronize()
+    assert rel(fNg.cpu().numpy().astype(np.float64), fN) <= (1e-12 if storage == "f64" else 1e-4)
+    assert rel(gfg.cpu().numpy(), gf) <= tol
+    assert rel(gsg.cpu().numpy(), gs) <= tol
+    assert rel(gug.cpu().numpy(), gu) <= tol
+    assert np.all(gsg.cpu().numpy()[:3] == 0)
+
+
+@pytest.mark.parametrize("lattice", ["d3q19", "d3q27"])
+def test_adjoint_3d_zero_and_field_fp64(lattice):
+    lat = oracle_lattice(lattice)
+    shape = (4, 5, 6)
+    rng = np.random.default_rng(5)
+    rho, u = workloads.taylor_green(6, 0.05, shape=shape)
+    f0 = A.equilibrium(lat, rho, u) * (1 + 0.01 * rng.uniform(-1, 1, (lat.q,) + shape))
+    s = workloads.RATES_D3Q19 if lattice == "d3q19" else workloads.RATES_D3Q27
+    field = (0.1 * rng.uniform(-1, 1, (3,) + shape)).astype(np.float32).astype(np.float64)
+    ctx = Lbmrv(lattice, s, (6, 5, 4), "f64")
+    for mode, fld in (("zero", None), ("field", field)):
+        n = 7
+        fN = A.run(lat, f0, s, n, mode=A.FIELD if fld is not None else A.ZERO, field=fld)
+        _, cot = E.kinetic_energy(lat, fN)
+        _, gf, gs, gu = E.vjp(lat, f0, s, n, cot, field=fld)
+        _, gfg, gsg, gug = ctx.adjoint(gpu(f0), gpu(cot), n, 3, mode,
+                                       None if fld is None else gpu(fld.astype(np.float32)))
+        torch.cuda.synchronize()
+        assert rel(gfg.cpu().numpy(), gf) <= 1e-10
+        assert rel(gsg.cpu().numpy(), gs) <= 1e-10
+        if fld is not None:
+            assert rel(gug.cpu().numpy(), gu) <= 1e-10
+
+
+def test_adjoint_rejects_fluid_mode():
+    ctx = Lbmrv("d2q9", workloads.RATES_D2Q9_GROUPED, (8, 8), "f32")
+    f = torch.zeros((9, 8, 8), device="cuda")
+    with pytest.raises(lbmrv.LbmrvError) as e:
+        ctx.adjoint(f, f, 3, 2, "fluid")
+    assert e.value.code == lbmrv.ERR_UNSUPPORTED
+
+
+def test_autograd_function_matches_adjoint_and_gradcheck():
+    """torch.autograd through lbmrv.steps gives the library adjoint, and FP64
+    gradcheck (finite differences of the GPU forward) passes on a tiny case."""
+    lat = oracle_lattice("d2q9")
+    L = 6
+    rng = np.random.default_rng(2)
+    rho = 1 + 0.01 * rng.standard_normal((L, L))
+    u = 0.03 * rng.uniform(-1, 1, (2, L, L))
+    f0 = A.equilibrium(lat, rho, u) * (1 + 0.05 * rng.uniform(-1, 1, (9, L, L)))
+    ctx = Lbmrv("d2q9", workloads.RATES_D2Q9_GROUPED, (L, L), "f64")
+    f0t = gpu(f0).requires_grad_(True)
+    st = torch.tensor(workloads.RATES_D2Q9_GROUPED, dtype=torch.float64, requires_grad=True)
+    fld = gpu(0.2 * rng.uniform(-1, 1, (2, L, L)), torch.float32).requires_grad_(True)
+
+    J = lbmrv.kinetic_energy(ctx, lbmrv.steps(f0t, st, fld, ctx, 4, 3))
+    J.backward()
+    fN = A.run(lat, f0, workloads.RATES_D2Q9_GROUPED, 4, mode=A.FIELD,
+               field=fld.detach().cpu().numpy().astype(np.float64))
+    _, cot = E.kinetic_energy(lat, fN)
+    _, gf, gs, gu = E.vjp(lat, f0, workloads.RATES_D2Q9_GROUPED, 4, cot,
+                          field=fld.detach().cpu().numpy().astype(np.float64))
+    assert rel(f0t.grad.cpu().numpy(), gf) <= 1e-10
+    assert rel(st.grad.numpy(), gs) <= 1e-10
+    assert rel(fld.grad.cpu().numpy().astype(np.float64), gu) <= 1e-6     # gradient returned as FP32
+
+    def fun(f, s_free):   # the conserved rates stay exactly 0 (section 1.1)
+        s = torch.cat([torch.zeros(3, dtype=torch.float64), s_free])
+        return lbmrv.kinetic_energy(ctx, lbmrv.steps(f, s, None, ctx, 3, 2))
+
+    s_in = torch.tensor([1.4, 1.7, 1.7, 1.2, 1.2, 1.4], dtype=torch.float64, requires_grad=True)
+    assert torch.autograd.gradcheck(fun, (gpu(f0).requires_grad_(True), s_in), eps=1e-6, atol=1e-8, rtol=1e-6)

@@ -23,6 +23,12 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS + % of HBM roofline (D3Q19 FP32 256³); adjoint cost ratio vs fwd"
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the fused collide-stream kernel (GB), from rocprofv3
+# FETCH_SIZE and WRITE_SIZE counters scaled by what the same counters read for
+# a plain copy of known size (FETCH x 2.0, WRITE x 1.0); see profiles/.  Only
+# valid for the kernel version the counters were taken on.
+TRAFFIC_GB = {("d3q19_tgv256_f32_fluid", "pull"): 2.5502}
+
 WORKLOADS = {
     # name: (lattice, dims, storage, mode, alpha, builder)
     "d3q19_tgv256_f32_fluid": ("d3q19", (256, 256, 256), "f32", "fluid"),
@@ -140,19 +146,17 @@ def adjoint_cost(torch, L=512, nsteps=2000, K=100, reps=2):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="d3q19_tgv256_f32_fluid", choices=sorted(WORKLOADS))
     ap.add_argument("--streaming", default="pull", choices=["pull", "push"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--traffic-gb", type=float, default=None,
-                    help="HBM bytes per launch of the dominant kernel from rocprofv3 counters (GB)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(domain decomposition is described in DESIGN.md, not implemented)", file=sys.stderr)
+              "(domain decomposition across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -213,7 +217,7 @@ def main():
                    "relative_velocity": mode, "streaming": args.streaming, "nodes": N},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": args.traffic_gb},
+                     "traffic": TRAFFIC_GB.get((name, args.streaming))},
         "state_finite": bool(finite),
         "wall_s": round(wall, 4),
     }

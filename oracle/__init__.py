@@ -8,8 +8,8 @@ every formula are written out here a second time, from the paper.
 
 Contents
 --------
-lattices   velocity sets, weights and moment bases (paper section 1.3 and the
-           three-dimensional readings documented in the design doc)
+lattices   velocity sets, weights and moment bases (paper section 1.3, and a
+           reading for three dimensions, where the paper has none)
 scheme     Oracle A: one time step as defined in section 1.2 (shifted moment
            matrix M(u~) evaluated from the polynomials, LU solve per node)
 mrt        Oracle C: the d'Humieres MRT step of section 1.1, written separately

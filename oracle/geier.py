@@ -12,8 +12,8 @@ Appendix B (proof of Proposition th:cascd2q9):
     s+- = (s_3 +- s_4)/2, then s_5 .. s_8;
   * g is found by block forward substitution: first the 2x2 system for
     (g_3, g_4), then the remaining components one at a time (eq. (casc2)).
-eq. (casc1) is garbled in the paper; this follows its stated conclusion
-(reading S7 in the design doc).  Indices here are 0-based.
+eq. (casc1) is garbled in the paper; this follows its stated conclusion.
+Indices here are 0-based.
 
 The rates ``s`` are indexed like the Geier basis of eq. (polgeier): s_3 on
 X^2+Y^2, s_4 on X^2-Y^2, s_5 on XY, s_6 on XY^2, s_7 on X^2Y, s_8 on X^2Y^2.

@@ -5,9 +5,9 @@ TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 The D2Q9 velocity order and its orthogonal polynomial family follow the paper,
 section 1.3 ("Two-dimensional examples"), eq. (mom).  The Geier family is
 eq. (polgeier) of Proposition th:cascd2q9.  The paper gives no three-dimensional
-lattice; the D3Q19/D3Q27 orders and the graded monomial bases below are the
-readings documented in the design doc (interface order, shared with the HIP library
-only as a written convention).
+lattice; the D3Q19/D3Q27 orders and the graded monomial bases below are a
+reading of it (the order is an interface convention, shared with the HIP
+library only as a written convention).
 
 A basis is a list of Python callables ``P(X, Y, Z, la)``.  They use only
 arithmetic operators, so they evaluate on NumPy arrays and on sympy symbols
@@ -39,7 +39,7 @@ D3Q27_C = [(0, 0, 0)] + _AXIS + _EDGE + _CORNER
 
 
 def _weights(cs, table):
-    """Standard weights by squared speed |c|^2 (equilibrium reading S2)."""
+    """Standard weights by squared speed |c|^2 (the equilibrium is a reading: the paper leaves it open)."""
     return [table[c[0] ** 2 + c[1] ** 2 + c[2] ** 2] for c in cs]
 
 
@@ -84,7 +84,7 @@ def _mono(a, b, c):
 
 
 # Degree-two block shared by both 3-D bases: bulk trace, two normal-stress
-# differences, three off-diagonal stresses (a reading).
+# differences, three off-diagonal stresses (a reading: the paper has no 3-D basis).
 _DEG2 = [
     lambda X, Y, Z, la: X ** 2 + Y ** 2 + Z ** 2,
     lambda X, Y, Z, la: 2 * X ** 2 - Y ** 2 - Z ** 2,

@@ -6,8 +6,8 @@ Follows section 1.2 of the paper step by step, in FP64, vectorised over nodes:
 
 1. conserved moments rho = sum_j f_j, q = sum_j v_j f_j, u = q / rho   eq. (rhoq)
 2. the relative velocity u~ (zero, alpha * u, or a given field)       section 1.2
-3. f^eq independent of u~ (second-order polynomial equilibrium,
-   reading S2 in the design doc)                                           section 1.2
+3. f^eq independent of u~ (second-order polynomial equilibrium, a
+   reading: the paper leaves f^eq open)                               section 1.2
 4. M(u~)_kj = P_k(v_j - u~) evaluated from the polynomials            eq. (MatMu)
 5. m = M(u~) f, m^eq = M(u~) f^eq                                     eq. (ftomu)
 6. m*_k = m_k + s_k (m^eq_k - m_k)                                    eq. (relaxationu)
@@ -39,8 +39,8 @@ def conserved(lat, f, la=1.0):
 def equilibrium(lat, rho, u, la=1.0):
     """f^eq_j = w_j rho [1 + v.u/cs2 + (v.u)^2/(2 cs2^2) - |u|^2/(2 cs2)], cs2 = la^2/3.
 
-    The paper leaves f^eq open ("any general equilibrium", section 2); this is
-    reading S2.  u has shape (d, *grid); returns (q, *grid).
+    The paper leaves f^eq open (section 2 allows a general equilibrium); this
+    is the usual second-order choice.  u has shape (d, *grid); returns (q, *grid).
     """
     v = lat.velocities(la)
     cs2 = la * la / 3.0

@@ -9,7 +9,7 @@
 #include <cstring>
 #include <new>
 
-#include "../../include/lbmrv.h"
+#include "lbmrv.h"
 #include "launch.hpp"
 
 namespace lbmrv {

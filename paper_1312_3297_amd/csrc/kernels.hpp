@@ -260,11 +260,18 @@ __global__ __launch_bounds__(256) void k_step(StepArgs<typename Store<ST>::T> a)
     collide_node<B, T, MODE>(h, a, utf);
   }
 
+  // Stores: the gather forms write their own node (aligned, contiguous per
+  // wavefront) and are streamed past the caches with non-temporal stores, which
+  // measured ~5% faster on MI355X for arrays far larger than L2 and MALL; the
+  // scatter form writes misaligned neighbours, where plain stores let L2 merge
+  // the partial lines and are faster.
   sfor<Q>([&](auto jj) {
     constexpr int J = jj;
-    uint32_t dst = own;
-    if constexpr (KIND == K_PUSH) dst = nbr(jj, std::integral_constant<int, 1>{});
-    fout[(uint64_t)J * N + dst] = S(h[J]);
+    if constexpr (KIND == K_PUSH) {
+      fout[(uint64_t)J * N + nbr(jj, std::integral_constant<int, 1>{})] = S(h[J]);
+    } else {
+      __builtin_nontemporal_store(S(h[J]), &fout[(uint64_t)J * N + own]);
+    }
   });
 }
 

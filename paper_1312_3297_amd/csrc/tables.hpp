@@ -478,7 +478,8 @@ constexpr Derived<B::Q> derive() {
     for (int k = 0; k < Q; ++k)            // strictly lower triangular
       for (int l = k; l < Q; ++l) t.ok_lower = t.ok_lower && D[ax].m[k][l].zero();
   }
-  // equilibrium moments in W coordinates (reading S2 of the equilibrium):
+  // equilibrium moments in W coordinates (second-order polynomial equilibrium;
+  // the paper leaves f^eq open):
   // f^eq_j = w_j rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 |u|^2)
   for (int j = 0; j < Q; ++j) t.w[j] = L::w(j);
   for (int k = 0; k < Q; ++k) {

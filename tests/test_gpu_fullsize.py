@@ -1,0 +1,101 @@
+"""Parity at the benchmark's full sizes, in the launch configurations it times.
+
+The whole grid runs on the GPU for n steps from a host-built initial state;
+the oracle then recomputes sampled output nodes one by one: the value of a node
+after n steps depends only on the (2n+1)^d block around it, so the oracle runs
+n steps on that block (periodic on the block; the wrapped values never reach the
+centre within n steps) and the centre is compared.  Samples include the domain
+faces and corners, where the periodic wrap of the GPU kernel is exercised.
+"""
+import numpy as np
+import pytest
+
+from oracle import scheme as A
+from paper_1312_3297_amd import workloads
+from paper_1312_3297_amd.lbmrv import Lbmrv
+
+from _common import from_storage, oracle_lattice, rel, to_storage
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+NSTEPS = 3
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _samples(shape, rng, n=120):
+    pts = [tuple(0 for _ in shape), tuple(s - 1 for s in shape)]
+    pts += [tuple(rng.integers(0, s) for s in shape) for _ in range(n)]
+    pts += [tuple((s - 1) if i == k else int(rng.integers(0, s)) for i, s in enumerate(shape))
+            for k in range(len(shape)) for _ in range(4)]
+    return pts
+
+
+def _block(arr, centre, R):
+    """Periodic (2R+1)^d block of arr[..., grid] around centre (grid axes last)."""
+    idx = [np.arange(c - R, c + R + 1) % s for c, s in zip(centre, arr.shape[-len(centre):])]
+    return arr[(Ellipsis,) + np.ix_(*idx)]
+
+
+def _check(lattice, shape, storage, mode, streaming, rates, rho, u, noise_amp, seed, field=None, tol=None):
+    lat = oracle_lattice(lattice)
+    f0 = A.equilibrium(lat, rho, u)
+    if noise_amp:
+        f0 += noise_amp * workloads.noise(lat.q, shape, seed)
+    st, f0w = to_storage(lat, f0, storage)
+    del f0
+    ctx = Lbmrv(lattice, rates, tuple(reversed(shape)), storage)
+    ctx.set_streaming(streaming)
+    fin = torch.from_numpy(st).to("cuda")
+    fout = torch.empty_like(fin)
+    fld = None if field is None else torch.from_numpy(field.astype(np.float32)).to("cuda")
+    ctx.step(fin, fout, mode, 1.0, fld, NSTEPS)
+    torch.cuda.synchronize()
+    got = fout.cpu().numpy()
+    del fin, fout
+    rng = np.random.default_rng(seed + 1)
+    R = NSTEPS
+    pts = _samples(shape, rng)
+    blocks = np.stack([_block(f0w, p, R) for p in pts], axis=1)               # (q, P, b, b[, b])
+    fblk = None
+    if field is not None:
+        fw = field.astype(np.float32).astype(np.float64)
+        fblk = np.stack([_block(fw, p, R) for p in pts], axis=1)
+    smode = {"zero": A.ZERO, "fluid": A.FLUID, "field": A.FIELD}[mode]
+    ref_all = []
+    for i in range(len(pts)):                     # oracle, one block at a time
+        fb = blocks[:, i]
+        out = A.run(lat, fb, rates, NSTEPS, mode=smode, field=None if fblk is None else fblk[:, i])
+        ref_all.append(out[(slice(None),) + (R,) * lat.d])
+    ref = np.stack(ref_all, axis=1)
+    gv = from_storage(lat, np.stack([got[(slice(None),) + p] for p in pts], axis=1), storage)
+    tol = tol if tol is not None else {"f64": 1e-12, "f32": 3e-7 * (NSTEPS + 4),
+                                       "f16dev": 8e-5 * (NSTEPS + 1)}[storage]
+    assert rel(gv, ref) <= tol
+
+
+@pytest.mark.parametrize("streaming", ["push", "pull"])
+def test_d3q19_taylor_green_256_f32_fluid(streaming):
+    rho, u = workloads.taylor_green(256, 0.05)
+    _check("d3q19", (256, 256, 256), "f32", "fluid", streaming, workloads.RATES_D3Q19, rho, u, 1e-5, 1313)
+
+
+def test_d3q19_taylor_green_256_f16dev_fluid():
+    rho, u = workloads.taylor_green(256, 0.05)
+    _check("d3q19", (256, 256, 256), "f16dev", "fluid", "push", workloads.RATES_D3Q19, rho, u, 1e-5, 1313)
+
+
+def test_d3q27_taylor_green_192_f32_field():
+    rho, u = workloads.taylor_green(192, 0.05)
+    _check("d3q27", (192, 192, 192), "f32", "field", "push", workloads.RATES_D3Q27, rho, u, 1e-5, 1314,
+           field=0.5 * u)
+
+
+def test_d2q9_double_shear_layer_2048_f32_fluid():
+    rho, u = workloads.double_shear_layer(2048)
+    _check("d2q9", (2048, 2048), "f32", "fluid", "push", workloads.RATES_D2Q9_SHEAR_LAYER, rho, u, 0.0, 7)

@@ -77,7 +77,7 @@ def test_shift_matrix_matches_appendix_A(la):
     """T(u~) = M(u~) M(0)^{-1} against the blocks of Appendix A (eq. (matTu)).
 
     Every printed block matches except D2, which the paper prints with 9/2 where
-    the definition (and the paper's own Maple procedure) gives 9 (reading S6).
+    the definition (and the paper's own Maple procedure) gives 9.
     """
     lat = lattices.make("d2q9")
     rng = np.random.default_rng(7)
@@ -142,7 +142,7 @@ def test_shift_structure_numeric(name):
 
 
 # --------------------------------------------------------------------------
-# equilibrium (reading S2)
+# equilibrium (the paper leaves it open; the usual second-order choice)
 # --------------------------------------------------------------------------
 
 def test_equilibrium_moments_d2q9_closed_form():

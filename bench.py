@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0
 # FETCH_SIZE and WRITE_SIZE counters scaled by what the same counters read for
 # a plain copy of known size (FETCH x 2.0, WRITE x 1.0); see profiles/.  Only
 # valid for the kernel version the counters were taken on.
-TRAFFIC_GB = {("d3q19_tgv256_f32_fluid", "pull"): 2.5502}
+TRAFFIC_GB = {("d3q19_tgv256_f32_fluid", "pull"): 2.5503}
 
 WORKLOADS = {
     # name: (lattice, dims, storage, mode, alpha, builder)

@@ -208,9 +208,18 @@ __device__ __forceinline__ void collide_node(T (&h)[B::Q], const StepArgs<T>& a,
 }
 
 // ------------------------------------------------------------------ step kernel
-// Grid: (ceil(nx / blockDim.x), ny, nz).  One thread = one node (x, y, z).
+// Grid: (ceil(nx / blockDim.x), ceil(ny / blockDim.y), nz).  One thread = one
+// node (x, y, z).  The gather forms run blocks of up to 1024 threads spanning
+// several consecutive rows (blockDim.y > 1), so that each block streams a few
+// KB of every population array contiguously; the scatter form uses one row.
+// (512 for FP64 storage, whose D3Q27 collision needs more than 128 registers)
+template <int ST>
+constexpr int step_max_threads() {
+  return ST == 0 ? 512 : 1024;
+}
+
 template <class B, int ST, int MODE, int KIND>
-__global__ __launch_bounds__(256) void k_step(StepArgs<typename Store<ST>::T> a) {
+__global__ __launch_bounds__(step_max_threads<ST>()) void k_step(StepArgs<typename Store<ST>::T> a) {
   using L = typename B::Lat;
   using S = typename Store<ST>::S;
   using T = typename Store<ST>::T;
@@ -218,8 +227,8 @@ __global__ __launch_bounds__(256) void k_step(StepArgs<typename Store<ST>::T> a)
   constexpr int D = L::D;
 
   const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t y = blockIdx.y, z = blockIdx.z;
-  if (x >= a.nx) return;
+  const uint32_t y = blockIdx.y * blockDim.y + threadIdx.y, z = blockIdx.z;
+  if (x >= a.nx || y >= a.ny) return;
   const uint32_t nx = a.nx, ny = a.ny, nz = a.nz;
   const uint32_t xm = x == 0 ? nx - 1 : x - 1;
   const uint32_t xp = x == nx - 1 ? 0 : x + 1;
@@ -249,7 +258,12 @@ __global__ __launch_bounds__(256) void k_step(StepArgs<typename Store<ST>::T> a)
     constexpr int J = jj;
     uint32_t src = own;
     if constexpr (KIND == K_PULL || KIND == K_STREAM) src = nbr(jj, std::integral_constant<int, -1>{});
-    h[J] = T(fin[(uint64_t)J * N + src]);
+    // loads that are aligned with the wavefront (own node, or a neighbour in y
+    // or z only) bypass the caches; the +-1 shifted ones along x share cache
+    // lines with the neighbouring wavefront and go through L2
+    constexpr bool aligned = (KIND == K_COLLIDE) || ((KIND == K_PULL || KIND == K_STREAM) && L::c[J].x == 0);
+    if constexpr (aligned) h[J] = T(__builtin_nontemporal_load(&fin[(uint64_t)J * N + src]));
+    else h[J] = T(fin[(uint64_t)J * N + src]);
   });
 
   if constexpr (KIND != K_STREAM) {

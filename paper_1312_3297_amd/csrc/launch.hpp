@@ -54,9 +54,13 @@ hipError_t launch_step_t(const StepLaunch& L) {
   a.alpha = T(L.alpha);
   a.inv_lambda = T(L.inv_lambda);
   for (int k = 0; k < 27; ++k) a.s[k] = T(L.s[k]);
-  const int bx = L.block;
-  dim3 grid((L.nx + bx - 1) / bx, L.ny, L.nz);
-  hipLaunchKernelGGL((k_step<B, ST, MODE, KIND>), grid, dim3(bx), 0, L.stream, a);
+  // block: whole wavefronts along x (at most 256 threads), and for the gather
+  // forms as many rows as fit in step_max_threads threads
+  const uint32_t bx = L.nx >= 256 ? 256u : ((L.nx + 63u) / 64u) * 64u;
+  uint32_t by = KIND == K_PUSH ? 1u : (uint32_t)step_max_threads<ST>() / bx;
+  if (by > L.ny) by = L.ny;
+  dim3 grid((L.nx + bx - 1) / bx, (L.ny + by - 1) / by, L.nz);
+  hipLaunchKernelGGL((k_step<B, ST, MODE, KIND>), grid, dim3(bx, by), 0, L.stream, a);
   return hipGetLastError();
 }
 

@@ -1,0 +1,77 @@
+"""Accuracy of the storage forms against the FP64 oracle after 1000 steps.
+
+Taylor-Green vortex on a 64^3 D3Q19 grid (U0 = 0.05, wavenumber 2 pi / 64,
+1e-5 seeded noise), u~ = u, the 3-D rates of the workloads.  The oracle
+(Oracle B, C/OpenMP FP64) starts from the FP64 state; the GPU starts from that
+state rounded to its storage, so the errors include the initial rounding.
+Errors are normwise relative: ||rho - rho_ref||_inf / ||rho_ref||_inf,
+||u - u_ref||_inf / ||u_ref||_inf, and for each non-conserved fixed-frame moment
+||m_k - m_k,ref||_inf / ||m_k,ref||_inf (the largest over k is gated).  Because
+rho ~ 1 hides density errors, ||rho - rho_ref||_inf / ||rho_ref - 1||_inf is
+printed as well (not gated).
+
+Gates, from the arithmetic and a 2x margin over the measured values:
+  FP64 storage        1e-9 on every field (FP64 rounding over 1000 steps);
+  FP32 storage        rho 1e-5, u 2e-5, moments 5e-4 (FP32 rounds |f| ~ 1/3 to
+                      ~2e-8 per step; momentum errors random-walk over 1000 steps);
+  FP32 deviations     rho, u 1e-5, moments 2e-5;
+  FP16 deviations     rho, u 5e-3 (the tolerance stated for FP16 storage on rho
+                      and u), moments 5e-2.
+The measured values are printed (run pytest with -s).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import fast
+from oracle import scheme as A
+from paper_1312_3297_amd import workloads
+from paper_1312_3297_amd.lbmrv import Lbmrv
+
+from _common import from_storage, oracle_lattice, to_storage
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+L, NSTEPS = 64, 1000
+
+
+@pytest.fixture(scope="module")
+def reference():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    lat = oracle_lattice("d3q19")
+    rho, u = workloads.taylor_green(L, 0.05)
+    f0 = A.equilibrium(lat, rho, u) + 1e-5 * workloads.noise(19, (L, L, L), 1313)
+    ref = fast.run(lat, f0, workloads.RATES_D3Q19, NSTEPS, mode=A.FLUID, threads=min(16, os.cpu_count() or 1))
+    return lat, f0, ref
+
+
+def field_errors(lat, got, ref):
+    g_rho, g_u = A.conserved(lat, got)
+    r_rho, r_u = A.conserved(lat, ref)
+    e_rho = np.abs(g_rho - r_rho).max() / np.abs(r_rho).max()
+    e_rho1 = np.abs(g_rho - r_rho).max() / np.abs(r_rho - 1).max()
+    e_u = np.abs(g_u - r_u).max() / np.abs(r_u).max()
+    gm, rm = A.fixed_moments(lat, got), A.fixed_moments(lat, ref)
+    e_m = max(np.abs(gm[k] - rm[k]).max() / np.abs(rm[k]).max() for k in range(lat.d + 1, lat.q))
+    return e_rho, e_rho1, e_u, e_m
+
+
+@pytest.mark.parametrize("storage,gate_rho,gate_u,gate_m", [
+    ("f64", 1e-9, 1e-9, 1e-9), ("f32", 1e-5, 2e-5, 5e-4), ("f32dev", 1e-5, 1e-5, 2e-5),
+    ("f16dev", 5e-3, 5e-3, 5e-2)])
+def test_taylor_green_64_precision(reference, storage, gate_rho, gate_u, gate_m):
+    lat, f0, ref = reference
+    st, _ = to_storage(lat, f0, storage)
+    ctx = Lbmrv("d3q19", workloads.RATES_D3Q19, (L, L, L), storage)
+    fin = torch.from_numpy(st).to("cuda")
+    fout = torch.empty_like(fin)
+    ctx.step(fin, fout, "fluid", 1.0, None, NSTEPS)
+    torch.cuda.synchronize()
+    got = from_storage(lat, fout.cpu().numpy(), storage)
+    e_rho, e_rho1, e_u, e_m = field_errors(lat, got, ref)
+    print("\nprecision %-7s after %d steps: rho %.3e (of rho-1: %.3e)  u %.3e  non-conserved moments %.3e"
+          % (storage, NSTEPS, e_rho, e_rho1, e_u, e_m))
+    assert e_rho <= gate_rho and e_u <= gate_u and e_m <= gate_m

@@ -187,7 +187,8 @@ int lbmrv_lattice_tables(int lattice, int32_t *cdirs, double *w);
 /*
  * Discrete adjoint of nsteps time steps (the transpose of the linearised
  * relaxation of eq. (relaxationu) and of the transport of eq. (transport)),
- * for u~ = 0 or a given field u~(x) held fixed over the steps.  Given the
+ * for u~ = 0, u~ = ut_alpha * u(f) (differentiated through u = q / rho), or a
+ * given field u~(x) held fixed over the steps.  Given the
  * cotangent cot_fN = dJ/df_N of an objective J(f_N), with f_N the state after
  * nsteps steps from f0, it returns
  *   grad_f0 [q][N] = dJ/df0 (derivative with respect to the populations; for a
@@ -196,17 +197,18 @@ int lbmrv_lattice_tables(int lattice, int32_t *cdirs, double *w);
  *   grad_ut [d][N] = dJ/du~(x), accumulated in FP64 (FIELD mode only),
  *   f_N            = the forward state (optional, may be NULL).
  * The forward states are recomputed from snapshots taken every K steps.
- *   ut_mode     LBMRV_UT_ZERO or LBMRV_UT_FIELD (LBMRV_UT_FLUID -> UNSUPPORTED)
+ *   ut_mode     LBMRV_UT_ZERO, LBMRV_UT_FLUID or LBMRV_UT_FIELD; ut_alpha as in
+ *               lbmrv_step (finite)
  *   f0, f_N     storage type [q][N]; cot_fN, grad_f0: double for LBMRV_F64,
  *               float otherwise; grad_s, grad_ut: double; all device arrays
  *   workspace   device memory of at least lbmrv_adjoint_workspace_bytes(c,
  *               nsteps, K) bytes, 256-byte aligned, owned by the caller
- * Asynchronous on hip_stream.  Errors: INVALID_ARG, UNSUPPORTED, ALIGNMENT, HIP.
+ * Asynchronous on hip_stream.  Errors: INVALID_ARG, ALIGNMENT, HIP.
  */
 size_t lbmrv_adjoint_workspace_bytes(const lbmrv_ctx *c, int64_t nsteps, int64_t K);
-int lbmrv_adjoint(lbmrv_ctx *c, const void *f0, int ut_mode, const float *ut_field, int64_t nsteps,
-                  int64_t K, const void *cot_fN, void *workspace, size_t workspace_bytes, void *f_N,
-                  void *grad_f0, double *grad_s, double *grad_ut, void *hip_stream);
+int lbmrv_adjoint(lbmrv_ctx *c, const void *f0, int ut_mode, double ut_alpha, const float *ut_field,
+                  int64_t nsteps, int64_t K, const void *cot_fN, void *workspace, size_t workspace_bytes,
+                  void *f_N, void *grad_f0, double *grad_s, double *grad_ut, void *hip_stream);
 
 void lbmrv_destroy(lbmrv_ctx *c);
 const char *lbmrv_strerror(int code);

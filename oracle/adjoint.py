@@ -6,8 +6,9 @@ The step is written once more with plain PyTorch CPU ops, following the same
 definition as Oracle A (section 1.2: M(u~)_kj = P_k(v_j - u~) from the
 polynomials, m* = m + s (m^eq - m), f* = M(u~)^{-1} m*, transport), and reverse-
 mode automatic differentiation of that definition gives the discrete adjoint:
-d/df_0, d/ds_k and d/du~(x) of J(f_N) for a cotangent dJ/df_N.  u~ is either
-zero or a given field held fixed over the N steps.  Segments of K steps are
+d/df_0, d/ds_k and d/du~(x) of J(f_N) for a cotangent dJ/df_N.  u~ is zero, a
+given field held fixed over the N steps, or alpha times the local fluid
+velocity (then autodiff also differentiates through u = q / rho).  Segments of K steps are
 recomputed during the backward pass (torch.utils.checkpoint), so memory stays
 bounded for long runs.
 """
@@ -22,8 +23,9 @@ def _basis_torch(lat, X, Y, Z, la):
     return torch.stack([P(X, Y, Z, la) for P in lat.basis], dim=-2)   # (..., q_basis, q_vel)
 
 
-def step(lat, f, s, la=1.0, field=None):
-    """One step in torch FP64.  f (q, *grid); s (q,); field (d, *grid) or None (u~ = 0)."""
+def step(lat, f, s, la=1.0, field=None, alpha=None):
+    """One step in torch FP64.  f (q, *grid); s (q,); field (d, *grid) or None;
+    u~ = field if given, else alpha * u if alpha is given, else 0."""
     q, d = lat.q, lat.d
     grid = f.shape[1:]
     F = f.reshape(q, -1).T                                             # (N, q)
@@ -36,10 +38,12 @@ def step(lat, f, s, la=1.0, field=None):
     vu = u @ v.T                                                        # (N, q)
     uu = (u * u).sum(dim=1, keepdim=True)
     feq = w[None, :] * rho[:, None] * (1 + vu / cs2 + vu * vu / (2 * cs2 * cs2) - uu / (2 * cs2))
-    if field is None:
-        ut = torch.zeros_like(u)
-    else:
+    if field is not None:
         ut = field.reshape(d, -1).T                                     # (N, d)
+    elif alpha is not None:
+        ut = alpha * u
+    else:
+        ut = torch.zeros_like(u)
     rel = [v[None, :, a] - ut[:, a:a + 1] for a in range(d)]           # components of v_j - u~
     while len(rel) < 3:
         rel.append(torch.zeros_like(rel[0]))
@@ -57,11 +61,11 @@ def step(lat, f, s, la=1.0, field=None):
     return torch.stack(out)
 
 
-def run(lat, f, s, nsteps, la=1.0, field=None, K=100):
+def run(lat, f, s, nsteps, la=1.0, field=None, K=100, alpha=None):
     """nsteps steps with recomputation in segments of K steps during backward."""
     def seg(fx, sx, fld, n):
         for _ in range(n):
-            fx = step(lat, fx, sx, la, fld)
+            fx = step(lat, fx, sx, la, fld, alpha)
         return fx
     done = 0
     while done < nsteps:
@@ -74,7 +78,7 @@ def run(lat, f, s, nsteps, la=1.0, field=None, K=100):
     return f
 
 
-def vjp(lat, f0, s, nsteps, cot_fN, la=1.0, field=None, K=100):
+def vjp(lat, f0, s, nsteps, cot_fN, la=1.0, field=None, K=100, alpha=None):
     """Gradients of <cot_fN, f_N> with respect to f0, s and the u~ field.
 
     Returns (f_N, dJ/df0, dJ/ds, dJ/dfield or None) as NumPy FP64 arrays.
@@ -82,7 +86,7 @@ def vjp(lat, f0, s, nsteps, cot_fN, la=1.0, field=None, K=100):
     f0t = torch.tensor(np.asarray(f0, dtype=np.float64), requires_grad=True)
     st = torch.tensor(np.asarray(s, dtype=np.float64), requires_grad=True)
     ft = None if field is None else torch.tensor(np.asarray(field, dtype=np.float64), requires_grad=True)
-    fN = run(lat, f0t, st, nsteps, la, ft, K)
+    fN = run(lat, f0t, st, nsteps, la, ft, K, alpha)
     fN.backward(torch.tensor(np.asarray(cot_fN, dtype=np.float64)))
     return (fN.detach().numpy(), f0t.grad.numpy(), st.grad.numpy(),
             None if ft is None else ft.grad.numpy())
@@ -101,8 +105,8 @@ def kinetic_energy(lat, f, la=1.0):
     return J, grad
 
 
-def objective_after(lat, f0, s, nsteps, la=1.0, field=None):
+def objective_after(lat, f0, s, nsteps, la=1.0, field=None, alpha=None):
     """J(f_N) with Oracle A's NumPy step (used for finite differences)."""
-    mode = A.ZERO if field is None else A.FIELD
-    fN = A.run(lat, f0, s, nsteps, la, mode, field=field)
+    mode = A.FIELD if field is not None else (A.FLUID if alpha is not None else A.ZERO)
+    fN = A.run(lat, f0, s, nsteps, la, mode, alpha=1.0 if alpha is None else alpha, field=field)
     return kinetic_energy(lat, fN, la)[0]

@@ -1,5 +1,6 @@
 // Adjoint of one time step (relaxation in the moving frame, then transport),
-// for a relative velocity that does not depend on f (zero or a given field).
+// for a relative velocity that is zero, a given field, or alpha times the local
+// fluid velocity (then u~ depends on f and its derivative enters lambda).
 //
 // Forward step at node x (scatter form, pre-collision states):
 //   f^{n+1}_j(x + c_j) = f*_j(x),
@@ -13,6 +14,8 @@
 //   dJ/ds_k   += z3_k (R T(u~) d0)_k
 //   dJ/du~_a  += z2 . D_a (R^{-1} S R v) - z5 . D_a v,   v = T(u~) d0
 // using d/du~_a T(u~) = -D_a T(u~) and that the D_a commute with T.
+// With u~ = alpha u(f): du~_a/dh_i = alpha (c_ia - u_a) / rho, so dJ/du~_a
+// (lattice units) is folded into lambda instead of being accumulated.
 #pragma once
 
 #include "kernels.hpp"
@@ -29,7 +32,7 @@ struct AdjArgs {
   double* partial;     // [nblocks][Q] FP64 accumulators of dJ/ds, one row per block
   uint32_t nx, ny, nz;
   uint64_t N;
-  T rho0, inv_lambda;
+  T rho0, inv_lambda, alpha;
   T s[27];
 };
 
@@ -41,7 +44,6 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
   using Tb = Tab<B>;
   constexpr int Q = B::Q;
   constexpr int D = L::D;
-  static_assert(MODE != UT_FLUID, "the adjoint takes u~ independent of f");
 
   const uint32_t xr = blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = xr < a.nx;
@@ -85,6 +87,8 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
   T ut[3] = {T(0), T(0), T(0)};
   if constexpr (MODE == UT_FIELD) {
     sfor<D>([&](auto al) { ut[al] = T(a.ut[(uint64_t)al * N + own]) * a.inv_lambda; });
+  } else if constexpr (MODE == UT_FLUID) {
+    sfor<D>([&](auto al) { ut[al] = a.alpha * u[al]; });
   }
 
   T v[Q];  // d0, then T(u~) d0
@@ -193,28 +197,31 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
     z5[K] = acc;
   });
 
-  // dJ/du~ (FIELD): z2 . D_a am - z5 . D_a v, per node, in physical units
-  if constexpr (MODE == UT_FIELD) {
-    if (active) {
-      sfor<D>([&](auto ax) {
-        constexpr int AX = ax;
-        T gsum = T(0);
-        sfor<Q>([&](auto kk) {
-          constexpr int K = kk;
-          constexpr auto row = Tb::t.sE[AX][1][K];
-          if constexpr (K > D && row.n > 0) {
-            T da = T(0), dv = T(0);
-            sfor<row.n>([&](auto i) {
-              axpy_c<row.val[i]>(da, am[row.col[i]]);
-              axpy_c<row.val[i]>(dv, v[row.col[i]]);
-            });
-            gsum = fmac(zz[K], da, gsum);
-            gsum = fmac(-z5[K], dv, gsum);
-          }
-        });
-        a.grad_ut[(uint64_t)AX * N + own] += double(gsum * a.inv_lambda);
+  // dJ/du~_a = z2 . D_a am - z5 . D_a v (lattice units): accumulated per node in
+  // physical units for a given field, folded into lambda for u~ = alpha u
+  T gut[3] = {T(0), T(0), T(0)};
+  if constexpr (MODE != UT_ZERO) {
+    sfor<D>([&](auto ax) {
+      constexpr int AX = ax;
+      T gsum = T(0);
+      sfor<Q>([&](auto kk) {
+        constexpr int K = kk;
+        constexpr auto row = Tb::t.sE[AX][1][K];
+        if constexpr (K > D && row.n > 0) {
+          T da = T(0), dv = T(0);
+          sfor<row.n>([&](auto i) {
+            axpy_c<row.val[i]>(da, am[row.col[i]]);
+            axpy_c<row.val[i]>(dv, v[row.col[i]]);
+          });
+          gsum = fmac(zz[K], da, gsum);
+          gsum = fmac(-z5[K], dv, gsum);
+        }
       });
-    }
+      gut[AX] = gsum;
+    });
+  }
+  if constexpr (MODE == UT_FIELD) {
+    if (active) sfor<D>([&](auto ax) { a.grad_ut[(uint64_t)ax * N + own] += double(gut[ax] * a.inv_lambda); });
   }
 
   // z6 = T(u~)^T z5
@@ -245,6 +252,9 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
       A0 = fmac(z5[K], lit<ak, T>() + quad, A0);
     }
   });
+  if constexpr (MODE == UT_FLUID) {
+    sfor<D>([&](auto al) { Bv[al] = fmac(a.alpha * irho, gut[al], Bv[al]); });
+  }
   if (active) {
     T* lo = a.lam_out;
     sfor<Q>([&](auto jj) {

@@ -452,12 +452,12 @@ size_t lbmrv_adjoint_workspace_bytes(const lbmrv_ctx* c, int64_t nsteps, int64_t
   return adj_plan(c, nsteps, K).total;
 }
 
-int lbmrv_adjoint(lbmrv_ctx* c, const void* f0, int ut_mode, const float* ut_field, int64_t nsteps, int64_t K,
-                  const void* cot_fN, void* workspace, size_t workspace_bytes, void* f_N, void* grad_f0,
+int lbmrv_adjoint(lbmrv_ctx* c, const void* f0, int ut_mode, double ut_alpha, const float* ut_field, int64_t nsteps,
+                  int64_t K, const void* cot_fN, void* workspace, size_t workspace_bytes, void* f_N, void* grad_f0,
                   double* grad_s, double* grad_ut, void* hip_stream) {
   if (!c) return LBMRV_ERR_INVALID_ARG;
-  if (ut_mode == LBMRV_UT_FLUID) return LBMRV_ERR_UNSUPPORTED;  // u~ must not depend on f
-  if (ut_mode != LBMRV_UT_ZERO && ut_mode != LBMRV_UT_FIELD) return LBMRV_ERR_INVALID_ARG;
+  if (ut_mode != LBMRV_UT_ZERO && ut_mode != LBMRV_UT_FLUID && ut_mode != LBMRV_UT_FIELD) return LBMRV_ERR_INVALID_ARG;
+  if (!std::isfinite(ut_alpha)) return LBMRV_ERR_INVALID_ARG;
   if (nsteps < 1 || K < 1) return LBMRV_ERR_INVALID_ARG;
   const size_t eb = elem_bytes(c->storage);
   const size_t tb = c->storage == LBMRV_F64 ? 8 : 4;
@@ -489,7 +489,7 @@ int lbmrv_adjoint(lbmrv_ctx* c, const void* f0, int ut_mode, const float* ut_fie
   hipError_t e;
   // forward sweep (scatter form, pre-collision states), keeping every K-th state
   for (int64_t t = 0; t < nsteps; ++t) {
-    e = run_kind(c, K_PUSH, state(t), state(t + 1), ut_mode, 0.0, ut_field, st);
+    e = run_kind(c, K_PUSH, state(t), state(t + 1), ut_mode, ut_alpha, ut_field, st);
     if (e != hipSuccess) return LBMRV_ERR_HIP;
   }
   if ((e = fill_zero(partial, P.nblocks * c->q, st)) != hipSuccess) return LBMRV_ERR_HIP;
@@ -506,6 +506,7 @@ int lbmrv_adjoint(lbmrv_ctx* c, const void* f0, int ut_mode, const float* ut_fie
   A.N = c->N;
   A.rho0 = c->rho0;
   A.inv_lambda = 1.0 / c->lambda;
+  A.alpha = ut_alpha;
   for (int k = 0; k < 27; ++k) A.s[k] = k < c->q ? c->s[k] : 0.0;
   A.stream = st;
   A.block = c->block;
@@ -516,7 +517,7 @@ int lbmrv_adjoint(lbmrv_ctx* c, const void* f0, int ut_mode, const float* ut_fie
     const int64_t t1 = (t0 + K < nsteps) ? t0 + K : nsteps;
     if (sg < P.nseg - 1) {
       for (int64_t t = t0; t + 1 < t1; ++t) {
-        e = run_kind(c, K_PUSH, state(t), state(t + 1), ut_mode, 0.0, ut_field, st);
+        e = run_kind(c, K_PUSH, state(t), state(t + 1), ut_mode, ut_alpha, ut_field, st);
         if (e != hipSuccess) return LBMRV_ERR_HIP;
       }
     }

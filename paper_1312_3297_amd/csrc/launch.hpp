@@ -142,7 +142,7 @@ struct AdjLaunch {
   double* partial;
   uint32_t nx, ny, nz;
   uint64_t N;
-  double rho0, inv_lambda;
+  double rho0, inv_lambda, alpha;
   double s[27];
   hipStream_t stream;
   int block;
@@ -164,6 +164,7 @@ hipError_t launch_adjoint_t(const AdjLaunch& L) {
   a.N = L.N;
   a.rho0 = T(L.rho0);
   a.inv_lambda = T(L.inv_lambda);
+  a.alpha = T(L.alpha);
   for (int k = 0; k < 27; ++k) a.s[k] = T(L.s[k]);
   const int bx = L.block;
   dim3 grid((L.nx + bx - 1) / bx, L.ny, L.nz);
@@ -174,6 +175,7 @@ hipError_t launch_adjoint_t(const AdjLaunch& L) {
 template <class B, int ST>
 hipError_t launch_adjoint_s(const AdjLaunch& L) {
   if (L.mode == UT_ZERO) return launch_adjoint_t<B, ST, UT_ZERO>(L);
+  if (L.mode == UT_FLUID) return launch_adjoint_t<B, ST, UT_FLUID>(L);
   if (L.mode == UT_FIELD) return launch_adjoint_t<B, ST, UT_FIELD>(L);
   return hipErrorInvalidValue;
 }

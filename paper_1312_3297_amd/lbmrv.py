@@ -41,8 +41,8 @@ _SIGS = {
     "lbmrv_export": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p]),
     "lbmrv_lattice_tables": (_c_int, [_c_int, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_c_double)]),
     "lbmrv_adjoint_workspace_bytes": (ctypes.c_size_t, [_c_void_p, _c_int64, _c_int64]),
-    "lbmrv_adjoint": (_c_int, [_c_void_p, _c_void_p, _c_int, _c_void_p, _c_int64, _c_int64, _c_void_p, _c_void_p,
-                               ctypes.c_size_t, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
+    "lbmrv_adjoint": (_c_int, [_c_void_p, _c_void_p, _c_int, _c_double, _c_void_p, _c_int64, _c_int64, _c_void_p,
+                               _c_void_p, ctypes.c_size_t, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
     "lbmrv_destroy": (None, [_c_void_p]),
     "lbmrv_strerror": (ctypes.c_char_p, [_c_int]),
 }
@@ -200,7 +200,7 @@ class Lbmrv:
         return int(library().lbmrv_adjoint_workspace_bytes(self._h, int(nsteps), int(K)))
 
     def adjoint(self, f0, cot_fN, nsteps, K=100, mode="zero", field=None, want_fN=False, workspace=None,
-                stream=None):
+                stream=None, alpha=1.0):
         """Discrete adjoint of nsteps steps: (f_N or None, dJ/df0, dJ/ds [FP64], dJ/du~ [FP64] or None)."""
         import torch
         dev = f0.device
@@ -212,7 +212,7 @@ class Lbmrv:
         grad_ut = torch.empty((self.d,) + self.grid_shape, dtype=torch.float64, device=dev) \
             if mode == "field" else None
         fN = self.empty(dev) if want_fN else None
-        _check(library().lbmrv_adjoint(self._h, _ptr(f0), MODES[mode], _ptr(field), int(nsteps), int(K),
+        _check(library().lbmrv_adjoint(self._h, _ptr(f0), MODES[mode], float(alpha), _ptr(field), int(nsteps), int(K),
                                        _ptr(cot_fN), _ptr(workspace), nbytes, _ptr(fN), _ptr(grad_f0),
                                        _ptr(grad_s), _ptr(grad_ut), _stream(stream)), "lbmrv_adjoint")
         return fN, grad_f0, grad_s, grad_ut
@@ -237,19 +237,21 @@ def _steps_function():
 
     class Steps(torch.autograd.Function):
         """f_N = N steps of the scheme from f0 with rates s and relative velocity
-        field u~ (None: u~ = 0).  backward() runs the library's discrete adjoint
-        (lbmrv_adjoint) and returns dJ/df0, dJ/ds (FP64) and dJ/du~."""
+        u~ = field (if given), alpha * u (if alpha is given) or 0.  backward()
+        runs the library's discrete adjoint (lbmrv_adjoint) and returns dJ/df0,
+        dJ/ds (FP64) and dJ/du~ (field case)."""
 
         @staticmethod
-        def forward(ctx, f0, s, field, lb, nsteps, K):
+        def forward(ctx, f0, s, field, lb, nsteps, K, alpha):
             lb.set_rates([float(x) for x in s.detach().cpu()])
-            mode = "zero" if field is None else "field"
+            mode = "field" if field is not None else ("fluid" if alpha is not None else "zero")
             fin = f0.detach().clone()
             fout = torch.empty_like(fin)
             fld = None if field is None else field.detach().contiguous()
-            lb.step(fin, fout, mode, 1.0, fld, nsteps)
+            a = 1.0 if alpha is None else float(alpha)
+            lb.step(fin, fout, mode, a, fld, nsteps)
             ctx.save_for_backward(f0, s, field if field is not None else torch.empty(0))
-            ctx.lb, ctx.nsteps, ctx.K, ctx.has_field = lb, nsteps, K, field is not None
+            ctx.lb, ctx.nsteps, ctx.K, ctx.mode, ctx.alpha = lb, nsteps, K, mode, a
             return fout
 
         @staticmethod
@@ -257,12 +259,12 @@ def _steps_function():
             f0, s, field = ctx.saved_tensors
             lb = ctx.lb
             lb.set_rates([float(x) for x in s.detach().cpu()])
-            mode = "field" if ctx.has_field else "zero"
             cot = grad_fN.detach().to(lb.compute_dtype).contiguous()
-            fld = field.detach().contiguous() if ctx.has_field else None
-            _, gf, gs, gu = lb.adjoint(f0.detach().contiguous(), cot, ctx.nsteps, ctx.K, mode, fld)
-            g_field = gu.to(field.dtype) if ctx.has_field else None
-            return gf.to(f0.dtype), gs.to(device=s.device, dtype=s.dtype), g_field, None, None, None
+            fld = field.detach().contiguous() if ctx.mode == "field" else None
+            _, gf, gs, gu = lb.adjoint(f0.detach().contiguous(), cot, ctx.nsteps, ctx.K, ctx.mode, fld,
+                                       alpha=ctx.alpha)
+            g_field = gu.to(field.dtype) if ctx.mode == "field" else None
+            return gf.to(f0.dtype), gs.to(device=s.device, dtype=s.dtype), g_field, None, None, None, None
 
     return Steps
 
@@ -270,12 +272,12 @@ def _steps_function():
 _STEPS = None
 
 
-def steps(f0, s, field, lb, nsteps, K=100):
+def steps(f0, s, field, lb, nsteps, K=100, alpha=None):
     """Differentiable N-step map (see Steps)."""
     global _STEPS
     if _STEPS is None:
         _STEPS = _steps_function()
-    return _STEPS.apply(f0, s, field, lb, nsteps, K)
+    return _STEPS.apply(f0, s, field, lb, nsteps, K, alpha)
 
 
 def kinetic_energy(lb, f):

@@ -83,12 +83,28 @@ def test_adjoint_3d_zero_and_field_fp64(lattice):
             assert rel(gug.cpu().numpy(), gu) <= 1e-10
 
 
-def test_adjoint_rejects_fluid_mode():
-    ctx = Lbmrv("d2q9", workloads.RATES_D2Q9_GROUPED, (8, 8), "f32")
-    f = torch.zeros((9, 8, 8), device="cuda")
-    with pytest.raises(lbmrv.LbmrvError) as e:
-        ctx.adjoint(f, f, 3, 2, "fluid")
-    assert e.value.code == lbmrv.ERR_UNSUPPORTED
+@pytest.mark.parametrize("lattice,storage,tol", [("d2q9", "f64", 1e-10), ("d3q19", "f64", 1e-10),
+                                                  ("d3q27", "f64", 1e-10), ("d2q9", "f32", 1e-4)])
+def test_adjoint_fluid_mode(lattice, storage, tol):
+    """u~ = alpha u(f), differentiated through u = q / rho."""
+    lat = oracle_lattice(lattice)
+    shape = (12, 13) if lat.d == 2 else (4, 5, 6)
+    rng = np.random.default_rng(6)
+    rho = 1 + 0.01 * rng.standard_normal(shape)
+    u = 0.05 * rng.uniform(-1, 1, (lat.d,) + shape)
+    f0 = A.equilibrium(lat, rho, u) * (1 + 0.05 * rng.uniform(-1, 1, (lat.q,) + shape))
+    st, f0w = to_storage(lat, f0, storage)
+    s = {9: workloads.RATES_D2Q9_GROUPED, 19: workloads.RATES_D3Q19, 27: workloads.RATES_D3Q27}[lat.q]
+    n, alpha = 9, 0.8
+    fN = A.run(lat, f0w, s, n, mode=A.FLUID, alpha=alpha)
+    _, cot = E.kinetic_energy(lat, fN)
+    _, gf, gs, _ = E.vjp(lat, f0w, s, n, cot, alpha=alpha, K=4)
+    ctx = Lbmrv(lattice, s, tuple(reversed(shape)), storage)
+    cdt = torch.float64 if storage == "f64" else torch.float32
+    _, gfg, gsg, _ = ctx.adjoint(gpu(st), gpu(cot, cdt), n, 4, "fluid", alpha=alpha)
+    torch.cuda.synchronize()
+    assert rel(gfg.cpu().numpy(), gf) <= tol
+    assert rel(gsg.cpu().numpy(), gs) <= tol
 
 
 def test_autograd_function_matches_adjoint_and_gradcheck():

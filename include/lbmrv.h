@@ -80,7 +80,7 @@ enum lbmrv_lattice { LBMRV_D2Q9 = 0, LBMRV_D3Q19 = 1, LBMRV_D3Q27 = 2 };
 enum lbmrv_basis { LBMRV_BASIS_DEFAULT = 0, LBMRV_BASIS_GEIER = 1 };
 enum lbmrv_storage { LBMRV_F64 = 0, LBMRV_F32 = 1, LBMRV_F32DEV = 2, LBMRV_F16DEV = 3 };
 enum lbmrv_utmode { LBMRV_UT_ZERO = 0, LBMRV_UT_FLUID = 1, LBMRV_UT_FIELD = 2 };
-enum lbmrv_streaming { LBMRV_STREAM_PULL = 0, LBMRV_STREAM_PUSH = 1 };
+enum lbmrv_streaming { LBMRV_STREAM_PULL = 0, LBMRV_STREAM_PUSH = 1, LBMRV_STREAM_AA = 2 };
 
 typedef struct lbmrv_ctx lbmrv_ctx;
 
@@ -106,12 +106,33 @@ int lbmrv_create(lbmrv_ctx **out, int lattice, int basis, double lambda, const d
 int lbmrv_set_rates(lbmrv_ctx *c, const double *s);
 
 /*
- * Select the streaming form used by lbmrv_step: LBMRV_STREAM_PULL (default:
- * each node gathers f*_j(x - c_j), the array holds post-collision values between
- * fused steps) or LBMRV_STREAM_PUSH (each node scatters to x + c_j, the array
- * holds pre-collision values).  Both give the same f(t + n dt).  No HIP call.
+ * Select the streaming form used by lbmrv_step.  All give the same f(t + n dt)
+ * bit for bit:
+ *   LBMRV_STREAM_PULL (default): each node gathers f*_j(x - c_j); two arrays,
+ *     post-collision values kept between fused passes;
+ *   LBMRV_STREAM_PUSH: each node scatters to x + c_j; two arrays;
+ *   LBMRV_STREAM_AA: one array updated in place (half the memory): even steps
+ *     store each post-collision population in its opposite slot at the node,
+ *     odd steps gather from the opposite slots upstream and scatter downstream;
+ *     an odd step count ends with one swap pass.  lbmrv_step then accepts
+ *     f_in == f_out (otherwise f_in is first copied to f_out).
+ * No HIP call.
  */
 int lbmrv_set_streaming(lbmrv_ctx *c, int kind);
+
+/*
+ * Half-way bounce-back walls on domain faces (the paper's analysis is for the
+ * whole space; walls are the usual closure).  Bit 2a + side of wall_mask makes
+ * the low (side 0) or high (side 1) face of axis a (0 = x, 1 = y, 2 = z) a
+ * wall placed half a node outside the last layer; other faces stay periodic.
+ * A population that would come from beyond a wall is the node's own
+ * post-collision opposite population plus 2 w_j rho_w (v_j . u_w) / cs2 for a
+ * wall moving at u_w (wall_u [6][3], physical units, face index 2a + side,
+ * NULL = all at rest); at an edge the first crossed wall face in axis order
+ * gives u_w.  Only the pull form supports walls (lbmrv_step returns
+ * UNSUPPORTED for the others, lbmrv_adjoint for any wall).  No HIP call.
+ */
+int lbmrv_set_walls(lbmrv_ctx *c, uint32_t wall_mask, const double *wall_u, double rho_w);
 
 /* Query: q, d, N (nodes), bytes per stored population. */
 int lbmrv_info(const lbmrv_ctx *c, int64_t *q, int64_t *d, int64_t *nodes, int64_t *bytes_per_pop);
@@ -119,10 +140,11 @@ int lbmrv_info(const lbmrv_ctx *c, int64_t *q, int64_t *d, int64_t *nodes, int64
 /*
  * Advance nsteps full time steps (relaxation then transport, section 1.2):
  * f_out <- f(t + nsteps dt) given f_in = f(t), both pre-collision.
- *   f_in, f_out  distinct device arrays of q*N elements of the storage type.
- *                f_in is the ping-pong partner and is overwritten (its
- *                contents are unspecified on return when nsteps >= 1).
- *                nsteps = 0 copies f_in to f_out.
+ *   f_in, f_out  device arrays of q*N elements of the storage type, distinct
+ *                except in the in-place form (LBMRV_STREAM_AA).  f_in is the
+ *                ping-pong partner and is overwritten (its contents are
+ *                unspecified on return when nsteps >= 1).  nsteps = 0 copies
+ *                f_in to f_out.
  *   ut_mode      LBMRV_UT_ZERO (u~ = 0), LBMRV_UT_FLUID (u~ = ut_alpha * u at
  *                every node and step; ut_alpha = 1 is the cascaded choice) or
  *                LBMRV_UT_FIELD (u~(x) read from ut_field, fixed over the call)
@@ -130,7 +152,7 @@ int lbmrv_info(const lbmrv_ctx *c, int64_t *q, int64_t *d, int64_t *nodes, int64
  *   ut_field     FIELD mode: device float array [d][N] (SoA, same node order),
  *                otherwise ignored (may be NULL)
  *   nsteps       >= 0
- * Errors: INVALID_ARG, ALIGNMENT, HIP.
+ * Errors: INVALID_ARG, UNSUPPORTED (walls with a non-pull form), ALIGNMENT, HIP.
  */
 int lbmrv_step(lbmrv_ctx *c, void *f_in, void *f_out, int ut_mode, double ut_alpha,
                const float *ut_field, int64_t nsteps, void *hip_stream);

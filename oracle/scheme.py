@@ -96,25 +96,64 @@ def collide(lat, f, s, la=1.0, mode=ZERO, alpha=1.0, field=None):
     return fstar.T.reshape(f.shape)
 
 
-def stream(lat, fstar):
-    """Transport phase, eq. (transport): f_j(x) = f*_j(x - c_j), periodic."""
+def opposite(lat):
+    """Index of -c_j for every j."""
+    return [next(k for k in range(lat.q) if all(lat.c[k] == -lat.c[j])) for j in range(lat.q)]
+
+
+def stream(lat, fstar, walls=None, la=1.0):
+    """Transport phase, eq. (transport): f_j(x) = f*_j(x - c_j), periodic.
+
+    walls: None, or (mask, uw, rho_w) for half-way bounce-back on domain faces
+    (the paper does not discuss boundaries; this is the usual rule).  Bit
+    2a + side of mask makes the low (side 0) or high (side 1) face of axis a a
+    wall; uw[2a + side] is that wall's velocity (length 3).  A population whose
+    source x - c_j lies beyond a wall face comes back from the node itself:
+    f_j(x) = f*_opp(j)(x) + 2 w_j rho_w (v_j . u_w) / cs2, taking u_w of the
+    first crossed wall face in axis order.
+    """
     out = np.empty_like(fstar)
     nd = fstar.ndim - 1
     for j in range(lat.q):
         shifts = [int(lat.c[j, a]) for a in range(lat.d)]
         axes = [nd - 1 - a for a in range(lat.d)]                # x -> last axis
         out[j] = np.roll(fstar[j], shift=shifts, axis=axes)
+    if walls is None or not walls[0]:
+        return out
+    mask, uw, rho_w = walls
+    opp = opposite(lat)
+    cs2 = la * la / 3.0
+    shape = fstar.shape[1:]
+    idx = np.meshgrid(*[np.arange(n) for n in shape], indexing="ij")
+    coord = list(reversed(idx))                                  # coord[a]: index along axis a
+    for j in range(lat.q):
+        hit = np.zeros(shape, dtype=bool)
+        face = np.full(shape, -1)
+        for a in range(lat.d):
+            c = int(lat.c[j, a])
+            for side, cond in ((0, c > 0), (1, c < 0)):
+                if cond and (mask >> (2 * a + side)) & 1:
+                    edge = coord[a] == (0 if side == 0 else shape[nd - 1 - a] - 1)
+                    face = np.where(edge & (face < 0), 2 * a + side, face)
+                    hit |= edge
+        if not hit.any():
+            continue
+        corr = np.zeros(shape)
+        for fc in range(2 * lat.d):
+            vu = la * sum(int(lat.c[j, a]) * uw[fc][a] for a in range(lat.d))
+            corr = np.where(face == fc, 2 * lat.w[j] * rho_w * vu / cs2, corr)
+        out[j] = np.where(hit, fstar[opp[j]] + corr, out[j])
     return out
 
 
-def step(lat, f, s, la=1.0, mode=ZERO, alpha=1.0, field=None):
+def step(lat, f, s, la=1.0, mode=ZERO, alpha=1.0, field=None, walls=None):
     """One full time step: relaxation then transport."""
-    return stream(lat, collide(lat, f, s, la, mode, alpha, field))
+    return stream(lat, collide(lat, f, s, la, mode, alpha, field), walls, la)
 
 
-def run(lat, f, s, nsteps, la=1.0, mode=ZERO, alpha=1.0, field=None):
+def run(lat, f, s, nsteps, la=1.0, mode=ZERO, alpha=1.0, field=None, walls=None):
     for _ in range(nsteps):
-        f = step(lat, f, s, la, mode, alpha, field)
+        f = step(lat, f, s, la, mode, alpha, field, walls)
     return f
 
 

@@ -50,6 +50,7 @@ namespace {
 
 using StepFn = hipError_t (*)(const StepLaunch&);
 using AdjFn = hipError_t (*)(const AdjLaunch&);
+using FinFn = hipError_t (*)(void*, uint32_t, uint32_t, uint32_t, uint64_t, hipStream_t);
 using MomFn = hipError_t (*)(const MomLaunch&);
 using ConsFn = hipError_t (*)(const void*, uint64_t, double*, hipStream_t);
 using InitFn = hipError_t (*)(const InitLaunch&);
@@ -62,6 +63,7 @@ struct Entry {
   InitFn init[3];
   ConvFn conv[3];
   AdjFn adj[3];
+  FinFn fin[3];
 };
 
 #define LBMRV_ENTRY(NAME)                                                                 \
@@ -71,7 +73,8 @@ struct Entry {
         {launch_conserve_##NAME##_f64, launch_conserve_##NAME##_f32, launch_conserve_##NAME##_f16}, \
         {launch_init_##NAME##_f64, launch_init_##NAME##_f32, launch_init_##NAME##_f16},   \
         {launch_convert_##NAME##_f64, launch_convert_##NAME##_f32, launch_convert_##NAME##_f16}, \
-        {launch_adjoint_##NAME##_f64, launch_adjoint_##NAME##_f32, launch_adjoint_##NAME##_f16} \
+        {launch_adjoint_##NAME##_f64, launch_adjoint_##NAME##_f32, launch_adjoint_##NAME##_f16}, \
+        {launch_aa_finish_##NAME##_f64, launch_aa_finish_##NAME##_f32, launch_aa_finish_##NAME##_f16} \
   }
 
 const Entry kEntries[4] = {LBMRV_ENTRY(d2q9_paper), LBMRV_ENTRY(d2q9_geier), LBMRV_ENTRY(d3q19),
@@ -96,6 +99,9 @@ struct lbmrv_ctx {
   double rho0;    // 0 unless a deviation storage
   double* partial = nullptr;  // kRedBlocks * 5 partial sums + 5 results (device)
   int partial_dev = -1;
+  uint32_t wall_mask = 0;     // half-way bounce-back faces (bit 2a + side)
+  double wall_u[6][3] = {};   // wall velocities (physical units)
+  double rho_w = 1.0;
 };
 
 namespace {
@@ -140,6 +146,9 @@ StepLaunch base_launch(const lbmrv_ctx* c, hipStream_t st) {
   L.alpha = 0;
   L.inv_lambda = 1.0 / c->lambda;
   for (int k = 0; k < 27; ++k) L.s[k] = k < c->q ? c->s[k] : 0.0;
+  L.wall_mask = c->wall_mask;
+  for (int f = 0; f < 6; ++f)
+    for (int ax = 0; ax < 3; ++ax) L.wall_coef[f][ax] = 6.0 * c->rho_w * c->wall_u[f][ax] / c->lambda;
   L.stream = st;
   L.block = c->block;
   return L;
@@ -214,8 +223,27 @@ int lbmrv_set_rates(lbmrv_ctx* c, const double* s) {
 }
 
 int lbmrv_set_streaming(lbmrv_ctx* c, int kind) {
-  if (!c || (kind != LBMRV_STREAM_PULL && kind != LBMRV_STREAM_PUSH)) return LBMRV_ERR_INVALID_ARG;
+  if (!c || (kind != LBMRV_STREAM_PULL && kind != LBMRV_STREAM_PUSH && kind != LBMRV_STREAM_AA))
+    return LBMRV_ERR_INVALID_ARG;
   c->streaming = kind;
+  return LBMRV_OK;
+}
+
+int lbmrv_set_walls(lbmrv_ctx* c, uint32_t wall_mask, const double* wall_u, double rho_w) {
+  if (!c) return LBMRV_ERR_INVALID_ARG;
+  if (wall_mask >> (2 * c->d)) return LBMRV_ERR_INVALID_ARG;  // faces of existing axes only
+  if (!std::isfinite(rho_w)) return LBMRV_ERR_INVALID_ARG;
+  double u[6][3] = {};
+  if (wall_u)
+    for (int f = 0; f < 6; ++f)
+      for (int ax = 0; ax < 3; ++ax) {
+        if (!std::isfinite(wall_u[3 * f + ax])) return LBMRV_ERR_INVALID_ARG;
+        u[f][ax] = (f < 2 * c->d && ax < c->d) ? wall_u[3 * f + ax] : 0.0;
+      }
+  c->wall_mask = wall_mask;
+  for (int f = 0; f < 6; ++f)
+    for (int ax = 0; ax < 3; ++ax) c->wall_u[f][ax] = u[f][ax];
+  c->rho_w = rho_w;
   return LBMRV_OK;
 }
 
@@ -234,9 +262,27 @@ int lbmrv_step(lbmrv_ctx* c, void* f_in, void* f_out, int ut_mode, double ut_alp
   const size_t eb = elem_bytes(c->storage);
   int rc;
   if ((rc = check_ptr(f_in, eb)) || (rc = check_ptr(f_out, eb))) return rc;
-  if (f_in == f_out || nsteps < 0) return LBMRV_ERR_INVALID_ARG;
+  if (nsteps < 0) return LBMRV_ERR_INVALID_ARG;
+  if (f_in == f_out && c->streaming != LBMRV_STREAM_AA) return LBMRV_ERR_INVALID_ARG;
   if ((rc = check_mode(c, ut_mode, ut_alpha, ut_field))) return rc;
+  if (c->wall_mask && c->streaming != LBMRV_STREAM_PULL) return LBMRV_ERR_UNSUPPORTED;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (c->streaming == LBMRV_STREAM_AA) {
+    // One array, in place: even steps collide at the node and store each
+    // population in its opposite slot, odd steps gather from the opposite slots
+    // upstream and scatter downstream; after an odd count one swap pass
+    // restores the natural layout.
+    if (f_in != f_out &&
+        hipMemcpyAsync(f_out, f_in, eb * c->q * c->N, hipMemcpyDeviceToDevice, st) != hipSuccess)
+      return LBMRV_ERR_HIP;
+    hipError_t e = hipSuccess;
+    for (int64_t t = 0; t < nsteps; ++t) {
+      e = run_kind(c, (t % 2 == 0) ? K_AA_EVEN : K_AA_ODD, f_out, f_out, ut_mode, ut_alpha, ut_field, st);
+      if (e != hipSuccess) return LBMRV_ERR_HIP;
+    }
+    if (nsteps % 2 == 1) e = kEntries[c->entry].fin[c->sk](f_out, c->nx, c->ny, c->nz, c->N, st);
+    return e == hipSuccess ? LBMRV_OK : LBMRV_ERR_HIP;
+  }
   if (nsteps == 0) {
     return hipMemcpyAsync(f_out, f_in, eb * c->q * c->N, hipMemcpyDeviceToDevice, st) == hipSuccess
                ? LBMRV_OK
@@ -459,6 +505,7 @@ int lbmrv_adjoint(lbmrv_ctx* c, const void* f0, int ut_mode, double ut_alpha, co
   if (ut_mode != LBMRV_UT_ZERO && ut_mode != LBMRV_UT_FLUID && ut_mode != LBMRV_UT_FIELD) return LBMRV_ERR_INVALID_ARG;
   if (!std::isfinite(ut_alpha)) return LBMRV_ERR_INVALID_ARG;
   if (nsteps < 1 || K < 1) return LBMRV_ERR_INVALID_ARG;
+  if (c->wall_mask) return LBMRV_ERR_UNSUPPORTED;  // the adjoint covers periodic domains
   const size_t eb = elem_bytes(c->storage);
   const size_t tb = c->storage == LBMRV_F64 ? 8 : 4;
   int rc;

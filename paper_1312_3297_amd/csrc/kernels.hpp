@@ -59,7 +59,13 @@ template <>
 struct Store<2> { using S = _Float16; using T = float; };  // FP16 deviations, FP32 arithmetic
 
 enum Mode { UT_ZERO = 0, UT_FLUID = 1, UT_FIELD = 2 };
-enum Kind { K_PULL = 0, K_PUSH = 1, K_COLLIDE = 2, K_STREAM = 3 };
+// K_PULL    gather f*_j(x - c_j), collide, store at x        (post-collision kept)
+// K_PUSH    load at x, collide, scatter to x + c_j           (pre-collision kept)
+// K_COLLIDE load at x, collide, store at x
+// K_STREAM  gather f_j(x - c_j), store at x (no collision)
+// K_AA_EVEN load slot j at x, collide, store slot opp(j) at x         (in place)
+// K_AA_ODD  load slot opp(j) at x - c_j, collide, store slot j at x + c_j (in place)
+enum Kind { K_PULL = 0, K_PUSH = 1, K_COLLIDE = 2, K_STREAM = 3, K_AA_EVEN = 4, K_AA_ODD = 5 };
 
 template <class T>
 struct StepArgs {
@@ -72,6 +78,8 @@ struct StepArgs {
   T alpha;          // FLUID mode: u~ = alpha u
   T inv_lambda;     // FIELD mode: u~ is given in physical units
   T s[27];          // relaxation rates of the user basis
+  uint32_t wall_mask;  // bit 2a+side: the low (0) / high (1) face of axis a is a wall
+  T wall_coef[6][3];   // 6 rho_w u_w / lambda per wall face (half-way bounce-back)
 };
 
 // ------------------------------------------------------------------ collision
@@ -253,18 +261,50 @@ __global__ __launch_bounds__(step_max_threads<ST>()) void k_step(StepArgs<typena
   S* fout = static_cast<S*>(a.fout);
   const uint64_t N = a.N;
 
+  constexpr bool gather = KIND == K_PULL || KIND == K_STREAM || KIND == K_AA_ODD;
   T h[Q];
   sfor<Q>([&](auto jj) {
     constexpr int J = jj;
+    constexpr int slot = KIND == K_AA_ODD ? opposite<L>(J) : J;
     uint32_t src = own;
-    if constexpr (KIND == K_PULL || KIND == K_STREAM) src = nbr(jj, std::integral_constant<int, -1>{});
+    if constexpr (gather) src = nbr(jj, std::integral_constant<int, -1>{});
     // loads that are aligned with the wavefront (own node, or a neighbour in y
     // or z only) bypass the caches; the +-1 shifted ones along x share cache
     // lines with the neighbouring wavefront and go through L2
-    constexpr bool aligned = (KIND == K_COLLIDE) || ((KIND == K_PULL || KIND == K_STREAM) && L::c[J].x == 0);
-    if constexpr (aligned) h[J] = T(__builtin_nontemporal_load(&fin[(uint64_t)J * N + src]));
-    else h[J] = T(fin[(uint64_t)J * N + src]);
+    constexpr bool aligned = KIND == K_COLLIDE || KIND == K_AA_EVEN || (gather && L::c[J].x == 0);
+    if constexpr (aligned) h[J] = T(__builtin_nontemporal_load(&fin[(uint64_t)slot * N + src]));
+    else h[J] = T(fin[(uint64_t)slot * N + src]);
   });
+  // half-way bounce-back on wall faces (pull forms only): a population whose
+  // source lies beyond a wall is the node's own post-collision opposite
+  // population, plus the momentum of a moving wall
+  if constexpr (KIND == K_PULL || KIND == K_STREAM) {
+    if (a.wall_mask) {
+      using Tb = Tab<B>;
+      const uint32_t pos[3] = {x, y, z}, ext[3] = {nx, ny, nz};
+      sfor<Q>([&](auto jj) {
+        constexpr int J = jj;
+        constexpr int cj[3] = {L::c[J].x, L::c[J].y, L::c[J].z};
+        int face = -1;
+        sfor<D>([&](auto ax) {
+          constexpr int c = cj[ax];
+          if constexpr (c > 0) {
+            if (face < 0 && ((a.wall_mask >> (2 * ax)) & 1u) && pos[ax] == 0) face = 2 * ax;
+          } else if constexpr (c < 0) {
+            if (face < 0 && ((a.wall_mask >> (2 * ax + 1)) & 1u) && pos[ax] == ext[ax] - 1) face = 2 * ax + 1;
+          }
+        });
+        if (face >= 0) {
+          constexpr T wj = lit<Tb::t.w[J], T>();
+          T cu = T(0);
+          sfor<D>([&](auto ax) {
+            if constexpr (cj[ax] != 0) cu = fmac(T(cj[ax]), a.wall_coef[face][ax], cu);
+          });
+          h[J] = fmac(wj, cu, T(fin[(uint64_t)opposite<L>(J) * N + own]));
+        }
+      });
+    }
+  }
 
   if constexpr (KIND != K_STREAM) {
     T utf[3] = {T(0), T(0), T(0)};
@@ -281,10 +321,42 @@ __global__ __launch_bounds__(step_max_threads<ST>()) void k_step(StepArgs<typena
   // the partial lines and are faster.
   sfor<Q>([&](auto jj) {
     constexpr int J = jj;
-    if constexpr (KIND == K_PUSH) {
+    if constexpr (KIND == K_PUSH || KIND == K_AA_ODD) {
       fout[(uint64_t)J * N + nbr(jj, std::integral_constant<int, 1>{})] = S(h[J]);
     } else {
-      __builtin_nontemporal_store(S(h[J]), &fout[(uint64_t)J * N + own]);
+      constexpr int slot = KIND == K_AA_EVEN ? opposite<L>(J) : J;
+      __builtin_nontemporal_store(S(h[J]), &fout[(uint64_t)slot * N + own]);
+    }
+  });
+}
+
+// After an even-form in-place step the array holds f*_j(x) in slot opp(j) at x;
+// the natural layout needs f_j(x) = f*_j(x - c_j).  Slots (j at x) and (opp(j)
+// at x - c_j) trade places, so one thread per node swaps one pair per
+// direction j with c_j > 0 in lexicographic order (each pair exactly once).
+template <class B, int ST>
+__global__ __launch_bounds__(256) void k_aa_finish(void* fp, uint32_t nx, uint32_t ny, uint32_t nz, uint64_t N) {
+  using L = typename B::Lat;
+  using S = typename Store<ST>::S;
+  constexpr int Q = B::Q;
+  const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t y = blockIdx.y, z = blockIdx.z;
+  if (x >= nx) return;
+  S* f = static_cast<S*>(fp);
+  const uint32_t own = (z * ny + y) * nx + x;
+  sfor<Q>([&](auto jj) {
+    constexpr int J = jj;
+    constexpr int cx = L::c[J].x, cy = L::c[J].y, cz = L::c[J].z;
+    constexpr bool positive = cz > 0 || (cz == 0 && (cy > 0 || (cy == 0 && cx > 0)));
+    if constexpr (positive) {
+      const uint32_t xs = cx == 0 ? x : (cx > 0 ? (x == 0 ? nx - 1 : x - 1) : (x == nx - 1 ? 0 : x + 1));
+      const uint32_t ys = cy == 0 ? y : (cy > 0 ? (y == 0 ? ny - 1 : y - 1) : (y == ny - 1 ? 0 : y + 1));
+      const uint32_t zs = cz == 0 ? z : (cz > 0 ? (z == 0 ? nz - 1 : z - 1) : (z == nz - 1 ? 0 : z + 1));
+      S* p = &f[(uint64_t)J * N + own];
+      S* q = &f[(uint64_t)opposite<L>(J) * N + (zs * ny + ys) * nx + xs];
+      const S t = *p;
+      *p = *q;
+      *q = t;
     }
   });
 }

@@ -24,6 +24,8 @@ struct StepLaunch {
   uint64_t N;
   double rho0, alpha, inv_lambda;
   double s[27];
+  uint32_t wall_mask;
+  double wall_coef[6][3];
   hipStream_t stream;
   int block;   // threads per block along x
 };
@@ -54,10 +56,14 @@ hipError_t launch_step_t(const StepLaunch& L) {
   a.alpha = T(L.alpha);
   a.inv_lambda = T(L.inv_lambda);
   for (int k = 0; k < 27; ++k) a.s[k] = T(L.s[k]);
+  a.wall_mask = L.wall_mask;
+  for (int f = 0; f < 6; ++f)
+    for (int ax = 0; ax < 3; ++ax) a.wall_coef[f][ax] = T(L.wall_coef[f][ax]);
   // block: whole wavefronts along x (at most 256 threads), and for the gather
   // forms as many rows as fit in step_max_threads threads
   const uint32_t bx = L.nx >= 256 ? 256u : ((L.nx + 63u) / 64u) * 64u;
-  uint32_t by = KIND == K_PUSH ? 1u : (uint32_t)step_max_threads<ST>() / bx;
+  // (FP16 storage measured faster with one row per block)
+  uint32_t by = (KIND == K_PUSH || KIND == K_AA_ODD || ST == 2) ? 1u : (uint32_t)step_max_threads<ST>() / bx;
   if (by > L.ny) by = L.ny;
   dim3 grid((L.nx + bx - 1) / bx, (L.ny + by - 1) / by, L.nz);
   hipLaunchKernelGGL((k_step<B, ST, MODE, KIND>), grid, dim3(bx, by), 0, L.stream, a);
@@ -71,8 +77,17 @@ hipError_t launch_step_m(const StepLaunch& L) {
     case K_PUSH: return launch_step_t<B, ST, MODE, K_PUSH>(L);
     case K_COLLIDE: return launch_step_t<B, ST, MODE, K_COLLIDE>(L);
     case K_STREAM: return launch_step_t<B, ST, UT_ZERO, K_STREAM>(L);
+    case K_AA_EVEN: return launch_step_t<B, ST, MODE, K_AA_EVEN>(L);
+    case K_AA_ODD: return launch_step_t<B, ST, MODE, K_AA_ODD>(L);
   }
   return hipErrorInvalidValue;
+}
+
+template <class B, int ST>
+hipError_t launch_aa_finish_t(void* f, uint32_t nx, uint32_t ny, uint32_t nz, uint64_t N, hipStream_t st) {
+  const uint32_t bx = nx >= 256 ? 256u : ((nx + 63u) / 64u) * 64u;
+  hipLaunchKernelGGL((k_aa_finish<B, ST>), dim3((nx + bx - 1) / bx, ny, nz), dim3(bx), 0, st, f, nx, ny, nz, N);
+  return hipGetLastError();
 }
 
 template <class B, int ST>
@@ -189,6 +204,8 @@ hipError_t launch_adjoint_s(const AdjLaunch& L) {
                                             hipStream_t st);                                \
   hipError_t launch_init_##NAME##_##SKN(const InitLaunch& L);                               \
   hipError_t launch_adjoint_##NAME##_##SKN(const AdjLaunch& L);                             \
+  hipError_t launch_aa_finish_##NAME##_##SKN(void* f, uint32_t nx, uint32_t ny, uint32_t nz, uint64_t N, \
+                                             hipStream_t st);                                \
   hipError_t launch_convert_##NAME##_##SKN(const void* in, void* out, double rho0, uint64_t N, \
                                            int to_storage, hipStream_t st);
 
@@ -203,6 +220,10 @@ hipError_t launch_adjoint_s(const AdjLaunch& L) {
   }                                                                                         \
   hipError_t launch_init_##NAME##_##SKN(const InitLaunch& L) { return launch_init_t<BASIS, ST>(L); } \
   hipError_t launch_adjoint_##NAME##_##SKN(const AdjLaunch& L) { return launch_adjoint_s<BASIS, ST>(L); } \
+  hipError_t launch_aa_finish_##NAME##_##SKN(void* f, uint32_t nx, uint32_t ny, uint32_t nz, uint64_t N, \
+                                             hipStream_t st) {                               \
+    return launch_aa_finish_t<BASIS, ST>(f, nx, ny, nz, N, st);                             \
+  }                                                                                         \
   hipError_t launch_convert_##NAME##_##SKN(const void* in, void* out, double rho0, uint64_t N, \
                                            int to_storage, hipStream_t st) {               \
     return launch_convert_t<BASIS, ST>(in, out, rho0, N, to_storage, st);                   \

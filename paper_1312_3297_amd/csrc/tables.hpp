@@ -301,6 +301,14 @@ struct D3Q27Lat {
   }
 };
 
+// Index of the opposite direction -c_j.
+template <class L>
+constexpr int opposite(int j) {
+  for (int k = 0; k < L::Q; ++k)
+    if (L::c[k].x == -L::c[j].x && L::c[k].y == -L::c[j].y && L::c[k].z == -L::c[j].z) return k;
+  return -1;
+}
+
 // ---------------------------------------------------------------- bases
 // Each basis provides P (user-facing, rates act on it) and W (working basis).
 

@@ -16,7 +16,7 @@ LATTICES = {"d2q9": 0, "d3q19": 1, "d3q27": 2}
 BASES = {"default": 0, "geier": 1}
 STORAGES = {"f64": 0, "f32": 1, "f32dev": 2, "f16dev": 3}
 MODES = {"zero": 0, "fluid": 1, "field": 2}
-STREAMING = {"pull": 0, "push": 1}
+STREAMING = {"pull": 0, "push": 1, "aa": 2}
 QD = {"d2q9": (9, 2), "d3q19": (19, 3), "d3q27": (27, 3)}
 
 _c_void_p = ctypes.c_void_p
@@ -29,6 +29,7 @@ _SIGS = {
                               ctypes.POINTER(_c_int64), _c_int, _c_double]),
     "lbmrv_set_rates": (_c_int, [_c_void_p, ctypes.POINTER(_c_double)]),
     "lbmrv_set_streaming": (_c_int, [_c_void_p, _c_int]),
+    "lbmrv_set_walls": (_c_int, [_c_void_p, ctypes.c_uint32, ctypes.POINTER(_c_double), _c_double]),
     "lbmrv_info": (_c_int, [_c_void_p] + [ctypes.POINTER(_c_int64)] * 4),
     "lbmrv_step": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_int, _c_double, _c_void_p, _c_int64, _c_void_p]),
     "lbmrv_collide": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_int, _c_double, _c_void_p, _c_void_p]),
@@ -156,6 +157,14 @@ class Lbmrv:
 
     def set_streaming(self, kind):
         _check(library().lbmrv_set_streaming(self._h, STREAMING[kind]), "lbmrv_set_streaming")
+
+    def set_walls(self, mask, wall_u=None, rho_w=1.0):
+        """Half-way bounce-back faces: bit 2a+side of mask; wall_u [6][3] or None."""
+        wu = None
+        if wall_u is not None:
+            flat = [float(v) for row in wall_u for v in row]
+            wu = (_c_double * 18)(*flat)
+        _check(library().lbmrv_set_walls(self._h, int(mask), wu, float(rho_w)), "lbmrv_set_walls")
 
     def step(self, f_in, f_out, mode="zero", alpha=1.0, field=None, nsteps=1, stream=None):
         _check(library().lbmrv_step(self._h, _ptr(f_in), _ptr(f_out), MODES[mode], float(alpha), _ptr(field),

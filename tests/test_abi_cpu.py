@@ -126,3 +126,20 @@ def test_strerror_names_every_code():
     lib = lbmrv.library()
     for code in (0, -1, -2, -4, -5, -6):
         assert lib.lbmrv_strerror(code).decode() != "unknown error code"
+
+
+def test_walls_and_streaming_validation_before_any_hip_call():
+    ctx = lbmrv.Lbmrv("d2q9", GOOD9, (8, 8), storage="f32")
+    lib = lbmrv.library()
+    assert lib.lbmrv_set_walls(ctx._h, 1 << 4, None, 1.0) == lbmrv.ERR_INVALID_ARG     # no z axis in 2-D
+    assert lib.lbmrv_set_walls(ctx._h, 0b1100, None, float("nan")) == lbmrv.ERR_INVALID_ARG
+    bad_u = (ctypes.c_double * 18)(*([0.0] * 17 + [float("inf")]))
+    assert lib.lbmrv_set_walls(ctx._h, 0b1100, bad_u, 1.0) == lbmrv.ERR_INVALID_ARG
+    assert lib.lbmrv_set_streaming(ctx._h, 2) == lbmrv.OK                               # in-place form
+    assert lib.lbmrv_set_walls(ctx._h, 0b1100, None, 1.0) == lbmrv.OK
+    a, b, st = ctypes.c_void_p(4096), ctypes.c_void_p(8192), ctypes.c_void_p(0)
+    assert lib.lbmrv_step(ctx._h, a, b, 0, 1.0, None, 1, st) == lbmrv.ERR_UNSUPPORTED   # walls need pull
+    assert lib.lbmrv_set_streaming(ctx._h, 0) == lbmrv.OK
+    assert lib.lbmrv_step(ctx._h, a, a, 0, 1.0, None, 1, st) == lbmrv.ERR_INVALID_ARG   # in place needs AA
+    assert lib.lbmrv_adjoint(ctx._h, a, 0, 1.0, None, 4, 2, b, ctypes.c_void_p(1 << 20), 1 << 30, None,
+                             ctypes.c_void_p(12288), ctypes.c_void_p(16384), None, st) == lbmrv.ERR_UNSUPPORTED

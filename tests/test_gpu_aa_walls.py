@@ -1,0 +1,102 @@
+"""The in-place (AA) streaming form and half-way bounce-back walls on the GPU.
+
+The in-place form must reproduce the two-array forms bit for bit (same per-node
+arithmetic, only the memory layout differs).  Walls are compared with the
+oracle's transport with walls (FP64, 1e-12) and must leave mass unchanged.
+"""
+import numpy as np
+import pytest
+
+from oracle import scheme as A
+from paper_1312_3297_amd import lbmrv, workloads
+from paper_1312_3297_amd.lbmrv import Lbmrv
+
+from _common import far_state, oracle_lattice, rel, to_storage
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+RATES = {9: workloads.RATES_D2Q9_GROUPED, 19: workloads.RATES_D3Q19, 27: workloads.RATES_D3Q27}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("lattice,storage", [("d2q9", "f32"), ("d3q19", "f32"), ("d3q27", "f64"),
+                                             ("d3q19", "f16dev")])
+@pytest.mark.parametrize("nsteps", [1, 4, 7])
+def test_in_place_form_matches_pull_bitwise(lattice, storage, nsteps):
+    lat = oracle_lattice(lattice)
+    shape = (21, 300) if lat.d == 2 else (5, 6, 70)
+    f0 = far_state(lat, shape, seed=11, amp=0.02, umax=0.08)
+    st, _ = to_storage(lat, f0, storage)
+    ctx = Lbmrv(lattice, RATES[lat.q], tuple(reversed(shape)), storage)
+    ref_in = torch.from_numpy(st).cuda()
+    ref_out = torch.empty_like(ref_in)
+    ctx.set_streaming("pull")
+    ctx.step(ref_in, ref_out, "fluid", 1.0, None, nsteps)
+    ctx.set_streaming("aa")
+    one = torch.from_numpy(st).cuda()
+    ctx.step(one, one, "fluid", 1.0, None, nsteps)              # in place, one array
+    a, b = torch.from_numpy(st).cuda(), torch.empty_like(ref_in)
+    ctx.step(a, b, "fluid", 1.0, None, nsteps)                  # two arrays: copy then in place
+    torch.cuda.synchronize()
+    assert torch.equal(one, ref_out)
+    assert torch.equal(b, ref_out)
+
+
+def _walls(lat):
+    """Walls on both y faces (the high one moving along x) and, in 3-D, on the low z face."""
+    mask = (1 << 2) | (1 << 3) | ((1 << 4) if lat.d == 3 else 0)
+    uw = [[0.0, 0.0, 0.0] for _ in range(6)]
+    uw[3] = [0.03, 0.0, 0.0]
+    return mask, uw
+
+
+@pytest.mark.parametrize("lattice", ["d2q9", "d3q19", "d3q27"])
+@pytest.mark.parametrize("mode", ["zero", "fluid"])
+def test_bounce_back_walls_match_oracle_fp64(lattice, mode):
+    lat = oracle_lattice(lattice)
+    shape = (9, 70) if lat.d == 2 else (5, 6, 7)
+    f0 = far_state(lat, shape, seed=13, amp=0.02, umax=0.05)
+    mask, uw = _walls(lat)
+    n = 6
+    ref = A.run(lat, f0, RATES[lat.q], n, mode={"zero": A.ZERO, "fluid": A.FLUID}[mode],
+                walls=(mask, uw, 1.0))
+    ctx = Lbmrv(lattice, RATES[lat.q], tuple(reversed(shape)), "f64")
+    ctx.set_walls(mask, uw, 1.0)
+    fin = torch.from_numpy(f0).cuda()
+    fout = torch.empty_like(fin)
+    ctx.step(fin, fout, mode, 1.0, None, n)
+    torch.cuda.synchronize()
+    assert rel(fout.cpu().numpy(), ref) <= 1e-12
+
+
+def test_walls_at_rest_conserve_mass_on_the_gpu():
+    lat = oracle_lattice("d3q19")
+    shape = (8, 9, 10)
+    rho, u = workloads.taylor_green(10, 0.03, shape=shape)
+    f0 = A.equilibrium(lat, rho, u)
+    ctx = Lbmrv("d3q19", RATES[19], (10, 9, 8), "f64")
+    ctx.set_walls(0b111111)
+    m0, _, _ = ctx.conservation(torch.from_numpy(f0).cuda())
+    fin = torch.from_numpy(f0).cuda()
+    fout = torch.empty_like(fin)
+    ctx.step(fin, fout, "fluid", 1.0, None, 100)
+    m1, _, ok = ctx.conservation(fout)
+    assert ok and abs(m1 - m0) <= 1e-12 * m0
+
+
+def test_walls_need_the_pull_form():
+    ctx = Lbmrv("d2q9", RATES[9], (8, 8), "f32")
+    ctx.set_walls(0b1100)
+    f = torch.zeros((9, 8, 8), device="cuda")
+    g = torch.empty_like(f)
+    for kind in ("push", "aa"):
+        ctx.set_streaming(kind)
+        with pytest.raises(lbmrv.LbmrvError) as e:
+            ctx.step(f, g, "zero", 1.0, None, 2)
+        assert e.value.code == lbmrv.ERR_UNSUPPORTED

@@ -362,3 +362,46 @@ def test_fp64_floor_between_two_oracles_on_the_64_shear_wave():
     assert np.abs(a - c).max() / np.abs(c).max() <= 1e-13
     ru = np.abs(ua - uc).max() / np.abs(uc).max()
     assert 1e-13 < ru <= 1e-11
+
+
+# --------------------------------------------------------------------------
+# half-way bounce-back walls (the usual closure; the paper treats the whole space)
+# --------------------------------------------------------------------------
+
+def _couette(name, mode, s, steps, ny=16, U=0.01):
+    lat = lattices.make(name)
+    shape = (ny, 4) if lat.d == 2 else (3, ny, 4)
+    mask = (1 << 2) | (1 << 3)                       # low and high y faces
+    uw = [[0.0, 0.0, 0.0] for _ in range(6)]
+    uw[3] = [U, 0.0, 0.0]                           # the high wall moves along x
+    f = A.equilibrium(lat, np.ones(shape), np.zeros((lat.d,) + shape))
+    m0 = f.sum()
+    for _ in range(steps):
+        f = A.step(lat, f, s, mode=mode, walls=(mask, uw, 1.0))
+    _, u = A.conserved(lat, f)
+    prof = u[0].mean(axis=-1) if lat.d == 2 else u[0].mean(axis=(0, 2))
+    return f.sum() - m0, prof
+
+
+@pytest.mark.parametrize("name,mode", [("d2q9", A.ZERO), ("d2q9", A.FLUID), ("d3q19", A.FLUID)])
+def test_couette_flow_is_linear_between_half_way_walls(name, mode):
+    """Steady Couette flow: u_x(y) = U (y + 1/2) / ny, walls half a node outside."""
+    lat = lattices.make(name)
+    s = [0, 0, 0, 1.4, 1.2, 1.2, 1.1, 1.1, 1.4] if lat.q == 9 else \
+        [0.0] * 4 + [1.1] + [1.2] * 5 + [1.5] * 6 + [1.2] * 3
+    drift, prof = _couette(name, mode, s, 3000)
+    y = np.arange(16)
+    assert abs(drift) <= 1e-11
+    assert np.abs(prof - 0.01 * (y + 0.5) / 16).max() <= 1e-4 * 0.01
+
+
+def test_walls_at_rest_conserve_mass_and_reflect():
+    lat = lattices.make("d2q9")
+    rng = np.random.default_rng(3)
+    f = rng.uniform(0.01, 0.2, (9, 6, 5))
+    fs = A.stream(lat, f, walls=(0b1111, [[0.0] * 3] * 4, 1.0))
+    assert abs(fs.sum() - f.sum()) <= 1e-14
+    # a population leaving through the low x wall comes back reversed at the same node
+    opp = A.opposite(lat)
+    j = 1                                            # c = (1, 0): its source at x = 0 is beyond the wall
+    assert np.array_equal(fs[j][:, 0], f[opp[j]][:, 0])

@@ -36,7 +36,11 @@ WORKLOADS = {
     "d3q27_tgv192_f32_field": ("d3q27", (192, 192, 192), "f32", "field"),
     "d2q9_shear2048_f32_fluid": ("d2q9", (2048, 2048), "f32", "fluid"),
     "d2q9_shear4096_f32_fluid": ("d2q9", (4096, 4096), "f32", "fluid"),
+    # channel between two half-way bounce-back walls (y faces), the upper one
+    # moving along x; Taylor-Green start as in the headline workload
+    "d3q19_couette256_f32_fluid_walls": ("d3q19", (256, 256, 256), "f32", "fluid"),
 }
+WALLS = {"d3q19_couette256_f32_fluid_walls": ((1 << 2) | (1 << 3), 0.05)}
 
 
 def build_state(name, ctx, torch):
@@ -149,7 +153,7 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="d3q19_tgv256_f32_fluid", choices=sorted(WORKLOADS))
-    ap.add_argument("--streaming", default="pull", choices=["pull", "push"])
+    ap.add_argument("--streaming", default="pull", choices=["pull", "push", "aa"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
@@ -166,8 +170,14 @@ def main():
     lattice, dims, storage, mode = WORKLOADS[name]
     ctx = Lbmrv(lattice, rates_for(lattice), dims, storage)
     ctx.set_streaming(args.streaming)
+    if name in WALLS:
+        mask, uwall = WALLS[name]
+        wu = [[0.0, 0.0, 0.0] for _ in range(6)]
+        wu[3] = [uwall, 0.0, 0.0]
+        ctx.set_walls(mask, wu, 1.0)
     f, field = build_state(name, ctx, torch)
-    g = torch.empty_like(f)
+    # the in-place form needs one array only
+    g = f if args.streaming == "aa" else torch.empty_like(f)
     stream = torch.cuda.current_stream()
 
     # warmup
@@ -193,9 +203,10 @@ def main():
     q = ctx.q
     b = {"f64": 8, "f32": 4, "f32dev": 4, "f16dev": 2}[storage]
     # kernel launches inside the call: pull = collide + (K-1) fused + transport;
-    # push = K fused (+ one split step when K is even).  Every launch reads and
-    # writes q populations per node.
-    launches = K + 1 if args.streaming == "pull" else (K if K % 2 else K + 1)
+    # push = K fused (+ one split step when K is even); in place = K (+ one swap
+    # pass when K is odd).  Every launch reads and writes q populations per node
+    # (the swap pass a little less).
+    launches = {"pull": K + 1, "push": K if K % 2 else K + 1, "aa": K + (K % 2)}[args.streaming]
     bytes_per_launch = 2 * q * b * N + (ctx.d * 4 * N if mode == "field" else 0)
     avg_launch_s = ms * 1e-3 / launches
     achieved = bytes_per_launch / avg_launch_s / 1e9

@@ -81,6 +81,7 @@ enum lbmrv_basis { LBMRV_BASIS_DEFAULT = 0, LBMRV_BASIS_GEIER = 1 };
 enum lbmrv_storage { LBMRV_F64 = 0, LBMRV_F32 = 1, LBMRV_F32DEV = 2, LBMRV_F16DEV = 3 };
 enum lbmrv_utmode { LBMRV_UT_ZERO = 0, LBMRV_UT_FLUID = 1, LBMRV_UT_FIELD = 2 };
 enum lbmrv_streaming { LBMRV_STREAM_PULL = 0, LBMRV_STREAM_PUSH = 1, LBMRV_STREAM_AA = 2 };
+enum lbmrv_equilibrium { LBMRV_EQ_POLYNOMIAL = 0, LBMRV_EQ_MAXWELLIAN = 1 };
 
 typedef struct lbmrv_ctx lbmrv_ctx;
 
@@ -119,6 +120,18 @@ int lbmrv_set_rates(lbmrv_ctx *c, const double *s);
  * No HIP call.
  */
 int lbmrv_set_streaming(lbmrv_ctx *c, int kind);
+
+/*
+ * Equilibrium moments the relaxation aims at:
+ *   LBMRV_EQ_POLYNOMIAL (default): m^eq(u~) = M(u~) f^eq with the second-order
+ *     polynomial f^eq documented above (section 1.2);
+ *   LBMRV_EQ_MAXWELLIAN: m^eq(u~)_k = rho E[P_k(xi - u~)] for xi distributed as
+ *     the continuous Maxwellian of density rho, velocity u and temperature cs2
+ *     (the equilibria of Geier's cascaded scheme, mentioned in the paper's
+ *     introduction).  Conserved moments are unchanged.
+ * lbmrv_adjoint supports the polynomial form only.  No HIP call.
+ */
+int lbmrv_set_equilibrium(lbmrv_ctx *c, int kind);
 
 /*
  * Half-way bounce-back walls on domain faces (the paper's analysis is for the

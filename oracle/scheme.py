@@ -82,15 +82,50 @@ def relative_velocity(lat, u, mode, alpha=1.0, field=None):
     raise ValueError(mode)
 
 
-def collide(lat, f, s, la=1.0, mode=ZERO, alpha=1.0, field=None):
-    """Relaxation phase of section 1.2 at every node; returns f* (q, *grid)."""
+def maxwellian_moments(lat, rho, u, ut, la=1.0, npts=5):
+    """m^eq(u~)_k = rho E[P_k(xi - u~)], xi ~ N(u, cs2 I), cs2 = la^2 / 3.
+
+    The continuous Maxwellian moments Geier's cascaded scheme relaxes towards
+    (introduction of the paper) instead of M(u~) f^eq; the expectation is taken
+    by tensor Gauss-Hermite quadrature (npts points per axis: exact for
+    polynomials of degree <= 2 npts - 1).  rho (N,), u and ut (N, d); returns (N, q).
+    """
+    x, w = np.polynomial.hermite_e.hermegauss(npts)     # weight exp(-x^2 / 2)
+    w = w / np.sqrt(2 * np.pi)
+    sigma = la / np.sqrt(3.0)
+    grids = np.meshgrid(*([x] * lat.d), indexing="ij")
+    wts = np.ones_like(grids[0])
+    for g in np.meshgrid(*([w] * lat.d), indexing="ij"):
+        wts = wts * g
+    pts = [g.ravel() for g in grids]                    # quadrature points, each (P,)
+    wts = wts.ravel()
+    XYZ = []
+    for a in range(3):
+        if a < lat.d:
+            XYZ.append(u[:, a:a + 1] + sigma * pts[a][None, :] - ut[:, a:a + 1])   # (N, P)
+        else:
+            XYZ.append(np.zeros((u.shape[0], wts.size)))
+    out = np.empty((u.shape[0], lat.q))
+    for k, P in enumerate(lat.basis):
+        out[:, k] = rho * (P(XYZ[0], XYZ[1], XYZ[2], la) * wts[None, :]).sum(axis=1)
+    return out
+
+
+def collide(lat, f, s, la=1.0, mode=ZERO, alpha=1.0, field=None, eq="polynomial"):
+    """Relaxation phase of section 1.2 at every node; returns f* (q, *grid).
+
+    eq = "polynomial": m^eq(u~) = M(u~) f^eq (section 1.2);
+    eq = "maxwellian": m^eq(u~) = the Maxwellian's moments (Geier's choice)."""
     s = np.asarray(s, dtype=np.float64)
     rho, u = conserved(lat, f, la)
     ut = relative_velocity(lat, u, mode, alpha, field)
-    feq = equilibrium(lat, rho, u, la)
     M = moment_matrix(lat, _flat(lat, ut), la)                  # (N, q, q)
     m = np.einsum("nkj,nj->nk", M, _flat(lat, f))               # shifted moments
-    meq = np.einsum("nkj,nj->nk", M, _flat(lat, feq))           # shifted equilibrium moments
+    if eq == "maxwellian":
+        meq = maxwellian_moments(lat, rho.ravel(), _flat(lat, u), _flat(lat, ut), la)
+    else:
+        feq = equilibrium(lat, rho, u, la)
+        meq = np.einsum("nkj,nj->nk", M, _flat(lat, feq))       # shifted equilibrium moments
     mstar = m + s[None, :] * (meq - m)
     fstar = np.linalg.solve(M, mstar[:, :, None])[:, :, 0]      # M(u~)^{-1} m*
     return fstar.T.reshape(f.shape)
@@ -146,14 +181,14 @@ def stream(lat, fstar, walls=None, la=1.0):
     return out
 
 
-def step(lat, f, s, la=1.0, mode=ZERO, alpha=1.0, field=None, walls=None):
+def step(lat, f, s, la=1.0, mode=ZERO, alpha=1.0, field=None, walls=None, eq="polynomial"):
     """One full time step: relaxation then transport."""
-    return stream(lat, collide(lat, f, s, la, mode, alpha, field), walls, la)
+    return stream(lat, collide(lat, f, s, la, mode, alpha, field, eq), walls, la)
 
 
-def run(lat, f, s, nsteps, la=1.0, mode=ZERO, alpha=1.0, field=None, walls=None):
+def run(lat, f, s, nsteps, la=1.0, mode=ZERO, alpha=1.0, field=None, walls=None, eq="polynomial"):
     for _ in range(nsteps):
-        f = step(lat, f, s, la, mode, alpha, field, walls)
+        f = step(lat, f, s, la, mode, alpha, field, walls, eq)
     return f
 
 

@@ -102,6 +102,7 @@ struct lbmrv_ctx {
   uint32_t wall_mask = 0;     // half-way bounce-back faces (bit 2a + side)
   double wall_u[6][3] = {};   // wall velocities (physical units)
   double rho_w = 1.0;
+  int equilibrium = LBMRV_EQ_POLYNOMIAL;
 };
 
 namespace {
@@ -147,6 +148,7 @@ StepLaunch base_launch(const lbmrv_ctx* c, hipStream_t st) {
   L.inv_lambda = 1.0 / c->lambda;
   for (int k = 0; k < 27; ++k) L.s[k] = k < c->q ? c->s[k] : 0.0;
   L.wall_mask = c->wall_mask;
+  L.eq_maxwell = c->equilibrium == LBMRV_EQ_MAXWELLIAN ? 1u : 0u;
   for (int f = 0; f < 6; ++f)
     for (int ax = 0; ax < 3; ++ax) L.wall_coef[f][ax] = 6.0 * c->rho_w * c->wall_u[f][ax] / c->lambda;
   L.stream = st;
@@ -226,6 +228,12 @@ int lbmrv_set_streaming(lbmrv_ctx* c, int kind) {
   if (!c || (kind != LBMRV_STREAM_PULL && kind != LBMRV_STREAM_PUSH && kind != LBMRV_STREAM_AA))
     return LBMRV_ERR_INVALID_ARG;
   c->streaming = kind;
+  return LBMRV_OK;
+}
+
+int lbmrv_set_equilibrium(lbmrv_ctx* c, int kind) {
+  if (!c || (kind != LBMRV_EQ_POLYNOMIAL && kind != LBMRV_EQ_MAXWELLIAN)) return LBMRV_ERR_INVALID_ARG;
+  c->equilibrium = kind;
   return LBMRV_OK;
 }
 
@@ -506,6 +514,7 @@ int lbmrv_adjoint(lbmrv_ctx* c, const void* f0, int ut_mode, double ut_alpha, co
   if (!std::isfinite(ut_alpha)) return LBMRV_ERR_INVALID_ARG;
   if (nsteps < 1 || K < 1) return LBMRV_ERR_INVALID_ARG;
   if (c->wall_mask) return LBMRV_ERR_UNSUPPORTED;  // the adjoint covers periodic domains
+  if (c->equilibrium != LBMRV_EQ_POLYNOMIAL) return LBMRV_ERR_UNSUPPORTED;  // and the polynomial equilibrium
   const size_t eb = elem_bytes(c->storage);
   const size_t tb = c->storage == LBMRV_F64 ? 8 : 4;
   int rc;

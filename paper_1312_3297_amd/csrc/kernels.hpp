@@ -80,6 +80,7 @@ struct StepArgs {
   T s[27];          // relaxation rates of the user basis
   uint32_t wall_mask;  // bit 2a+side: the low (0) / high (1) face of axis a is a wall
   T wall_coef[6][3];   // 6 rho_w u_w / lambda per wall face (half-way bounce-back)
+  uint32_t eq_maxwell; // 1: equilibrium moments of the continuous Maxwellian
 };
 
 // ------------------------------------------------------------------ collision
@@ -117,6 +118,23 @@ __device__ __forceinline__ void collide_node(T (&h)[B::Q], const StepArgs<T>& a,
     sfor<D>([&](auto al) { ut[al] = utf[al]; });
   }
 
+  // Maxwellian option: per-axis moments E[xi^n] of N(u_a, cs2), cs2 = 1/3 in
+  // lattice units, n = 0..4 (a uniform branch; unused by the polynomial form)
+  T mu[3][kP];
+  const bool maxwell = a.eq_maxwell != 0;
+  if (maxwell) {
+    constexpr T cs2 = T(1) / T(3);
+    sfor<3>([&](auto ax) {
+      const T v = ax < D ? u[ax] : T(0);
+      const T v2 = v * v;
+      mu[ax][0] = T(1);
+      mu[ax][1] = v;
+      mu[ax][2] = v2 + cs2;
+      mu[ax][3] = v * (v2 + T(3) * cs2);
+      mu[ax][4] = v2 * (v2 + T(6) * cs2) + T(3) * cs2 * cs2;
+    });
+  }
+
   // fixed-frame non-equilibrium moments in the working basis (k > d only;
   // the conserved entries are exactly zero because f^eq has the same rho, j)
   T dl[Q];
@@ -129,6 +147,18 @@ __device__ __forceinline__ void collide_node(T (&h)[B::Q], const StepArgs<T>& a,
       sfor<Tb::t.sMW[K].n>([&](auto i) {
         axpy_c<Tb::t.sMW[K].val[i]>(mh, h[Tb::t.sMW[K].col[i]]);
       });
+      if (maxwell) {
+        // rho E[W_K(xi)] - rho0 a_K, with the monomial terms of W_K
+        constexpr Poly pk = B::W(K);
+        T mk = T(0);
+        sfor<pk.n>([&](auto ti) {
+          constexpr PTerm tm = pk.t[ti];
+          mk = fmac(lit<tm.c, T>(), mu[0][tm.a] * mu[1][tm.b] * mu[2][tm.e], mk);
+        });
+        constexpr Rat ak = Tb::t.a[K];
+        dl[K] = fmac(rho, mk, -(lit<ak, T>() * a.rho0)) - mh;
+        return;
+      }
       T quad = T(0);
       sfor<D>([&](auto al) {
         constexpr Rat bb = Tb::t.b[K][al];

@@ -26,6 +26,7 @@ struct StepLaunch {
   double s[27];
   uint32_t wall_mask;
   double wall_coef[6][3];
+  uint32_t eq_maxwell;
   hipStream_t stream;
   int block;   // threads per block along x
 };
@@ -57,6 +58,7 @@ hipError_t launch_step_t(const StepLaunch& L) {
   a.inv_lambda = T(L.inv_lambda);
   for (int k = 0; k < 27; ++k) a.s[k] = T(L.s[k]);
   a.wall_mask = L.wall_mask;
+  a.eq_maxwell = L.eq_maxwell;
   for (int f = 0; f < 6; ++f)
     for (int ax = 0; ax < 3; ++ax) a.wall_coef[f][ax] = T(L.wall_coef[f][ax]);
   // block: whole wavefronts along x (at most 256 threads), and for the gather

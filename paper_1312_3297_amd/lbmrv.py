@@ -17,6 +17,7 @@ BASES = {"default": 0, "geier": 1}
 STORAGES = {"f64": 0, "f32": 1, "f32dev": 2, "f16dev": 3}
 MODES = {"zero": 0, "fluid": 1, "field": 2}
 STREAMING = {"pull": 0, "push": 1, "aa": 2}
+EQUILIBRIA = {"polynomial": 0, "maxwellian": 1}
 QD = {"d2q9": (9, 2), "d3q19": (19, 3), "d3q27": (27, 3)}
 
 _c_void_p = ctypes.c_void_p
@@ -30,6 +31,7 @@ _SIGS = {
     "lbmrv_set_rates": (_c_int, [_c_void_p, ctypes.POINTER(_c_double)]),
     "lbmrv_set_streaming": (_c_int, [_c_void_p, _c_int]),
     "lbmrv_set_walls": (_c_int, [_c_void_p, ctypes.c_uint32, ctypes.POINTER(_c_double), _c_double]),
+    "lbmrv_set_equilibrium": (_c_int, [_c_void_p, _c_int]),
     "lbmrv_info": (_c_int, [_c_void_p] + [ctypes.POINTER(_c_int64)] * 4),
     "lbmrv_step": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_int, _c_double, _c_void_p, _c_int64, _c_void_p]),
     "lbmrv_collide": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_int, _c_double, _c_void_p, _c_void_p]),
@@ -157,6 +159,9 @@ class Lbmrv:
 
     def set_streaming(self, kind):
         _check(library().lbmrv_set_streaming(self._h, STREAMING[kind]), "lbmrv_set_streaming")
+
+    def set_equilibrium(self, kind):
+        _check(library().lbmrv_set_equilibrium(self._h, EQUILIBRIA[kind]), "lbmrv_set_equilibrium")
 
     def set_walls(self, mask, wall_u=None, rho_w=1.0):
         """Half-way bounce-back faces: bit 2a+side of mask; wall_u [6][3] or None."""

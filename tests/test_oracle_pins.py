@@ -405,3 +405,66 @@ def test_walls_at_rest_conserve_mass_and_reflect():
     opp = A.opposite(lat)
     j = 1                                            # c = (1, 0): its source at x = 0 is beyond the wall
     assert np.array_equal(fs[j][:, 0], f[opp[j]][:, 0])
+
+
+# --------------------------------------------------------------------------
+# Maxwellian equilibrium moments (Geier's choice, introduction of the paper)
+# --------------------------------------------------------------------------
+
+def test_maxwellian_central_moments_geier_basis():
+    """At u~ = u the Maxwellian's central moments are rho (1, 0, 0, 2cs2, 0, 0, 0, 0, cs2^2)."""
+    lat = lattices.make("d2q9_geier")
+    rng = np.random.default_rng(12)
+    for la in (1.0, 1.5):
+        rho = 1 + 0.05 * rng.standard_normal(6)
+        u = la * 0.2 * rng.uniform(-1, 1, (6, 2))
+        m = A.maxwellian_moments(lat, rho, u, u, la)
+        cs2 = la * la / 3
+        expect = np.array([1, 0, 0, 2 * cs2, 0, 0, 0, 0, cs2 * cs2])
+        assert np.allclose(m / rho[:, None], expect[None, :], atol=1e-14)
+
+
+def test_maxwellian_raw_moments_closed_form():
+    """At u~ = 0: E[X^2 Y^2] = (ux^2 + cs2)(uy^2 + cs2), E[X^2 Y] = (ux^2 + cs2) uy, ..."""
+    lat = lattices.make("d2q9_geier")
+    rng = np.random.default_rng(13)
+    rho = np.ones(5)
+    u = 0.3 * rng.uniform(-1, 1, (5, 2))
+    m = A.maxwellian_moments(lat, rho, u, np.zeros_like(u))
+    ux, uy, cs2 = u[:, 0], u[:, 1], 1 / 3
+    assert np.allclose(m[:, 3], ux ** 2 + uy ** 2 + 2 * cs2, atol=1e-15)
+    assert np.allclose(m[:, 6], ux * (uy ** 2 + cs2), atol=1e-15)
+    assert np.allclose(m[:, 7], (ux ** 2 + cs2) * uy, atol=1e-15)
+    assert np.allclose(m[:, 8], (ux ** 2 + cs2) * (uy ** 2 + cs2), atol=1e-15)
+
+
+@pytest.mark.parametrize("name", lattices.ALL)
+def test_maxwellian_collision_conserves_mass_momentum(name):
+    lat = lattices.make(name)
+    rng = np.random.default_rng(14)
+    shape = (3, 4) if lat.d == 2 else (2, 3, 4)
+    f = far_from_eq(lat, shape, rng)
+    fs = A.collide(lat, f, random_rates(lat, rng), 1.0, A.FLUID, 0.6, eq="maxwellian")
+    assert np.abs(fs.sum(0) - f.sum(0)).max() <= 1e-14
+    for a in range(lat.d):
+        assert np.abs(np.tensordot(lat.c[:, a].astype(float), fs - f, 1)).max() <= 1e-14
+
+
+def test_maxwellian_keeps_the_shear_viscosity():
+    """Second-order moments of the two equilibria agree, so nu is unchanged."""
+    lat = lattices.make("d2q9_geier")
+    s = [0, 0, 0, 1.4, 1.7, 1.7, 1.2, 1.2, 1.4]
+    L, U = 32, 1e-3
+    y = np.arange(L)
+    u = np.zeros((2, L, L))
+    u[0] = (U * np.sin(2 * np.pi * y / L))[:, None]
+    f = A.equilibrium(lat, np.ones((L, L)), u)
+    amps, ts = [], []
+    for t in range(301):
+        if t >= 50 and t % 25 == 0:
+            _, uu = A.conserved(lat, f)
+            amps.append(2 / L * np.sum(uu[0].mean(axis=-1) * np.sin(2 * np.pi * y / L)))
+            ts.append(t)
+        f = A.step(lat, f, s, mode=A.FLUID, eq="maxwellian")
+    nu = -np.polyfit(ts, np.log(amps), 1)[0] / (2 * np.pi / L) ** 2
+    assert abs(nu / ((1 / 1.7 - 0.5) / 3) - 1) < 5e-3

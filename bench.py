@@ -147,6 +147,14 @@ def adjoint_cost(torch, L=512, nsteps=2000, K=100, reps=2):
             "forward_ms": round(f_ms, 3), "adjoint_ms": round(a_ms, 3), "cost_ratio": round(a_ms / f_ms, 3)}
 
 
+def adjoint_costs(torch):
+    """The adjoint workload (512^2, N = 2000, K = 100), and the same at 2048^2
+    with N = 200 where launch overheads no longer weigh."""
+    out = adjoint_cost(torch)
+    out["at_2048"] = adjoint_cost(torch, L=2048, nsteps=200, K=100, reps=2)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,7 +241,7 @@ def main():
         "wall_s": round(wall, 4),
     }
     if not args.no_adjoint:
-        out["adjoint"] = adjoint_cost(torch)
+        out["adjoint"] = adjoint_costs(torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(name, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -147,6 +147,17 @@ int lbmrv_set_equilibrium(lbmrv_ctx *c, int kind);
  */
 int lbmrv_set_walls(lbmrv_ctx *c, uint32_t wall_mask, const double *wall_u, double rho_w);
 
+/*
+ * Replay of repeated step launches through HIP graphs (default off): the first
+ * lbmrv_step call with a given pair of arrays, mode and parameters captures 16
+ * consecutive passes into a graph on an internal stream (ordered after and
+ * before hip_stream with events) and later calls replay it.  Results are
+ * identical either way.  On MI355X direct launches already cost only ~4 us per
+ * pass and graph replay measured slower for small grids, hence off by default.
+ * No HIP call.
+ */
+int lbmrv_set_graphs(lbmrv_ctx *c, int enable);
+
 /* Query: q, d, N (nodes), bytes per stored population. */
 int lbmrv_info(const lbmrv_ctx *c, int64_t *q, int64_t *d, int64_t *nodes, int64_t *bytes_per_pop);
 

@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "lbmrv.h"
 #include "launch.hpp"
@@ -103,6 +104,23 @@ struct lbmrv_ctx {
   double wall_u[6][3] = {};   // wall velocities (physical units)
   double rho_w = 1.0;
   int equilibrium = LBMRV_EQ_POLYNOMIAL;
+  // replay of repeated launches through HIP graphs (see run_alternating)
+  struct GraphEntry {
+    int kind_a, kind_b;
+    const void* p;
+    const void* q;
+    int mode;
+    double alpha;
+    const float* field;
+    uint64_t version;
+    hipGraphExec_t exec;
+  };
+  int graphs_on = 0;
+  int graph_dev = -1;
+  uint64_t version = 0;  // bumped whenever kernel arguments change
+  hipStream_t gstream = nullptr;
+  hipEvent_t gev[2] = {nullptr, nullptr};
+  std::vector<GraphEntry> graphs;
 };
 
 namespace {
@@ -168,6 +186,75 @@ hipError_t run_kind(const lbmrv_ctx* c, int kind, const void* fin, void* fout, i
   return kEntries[c->entry].step[c->sk](L);
 }
 
+// Launch count kernels alternating (kind_a: p -> q) and (kind_b: q -> p),
+// starting with the first; p == q for the in-place form.  With graphs on and
+// count >= kGraphChunk, a graph of kGraphChunk such launches is captured once
+// per (kinds, buffers, mode, alpha, field, argument version) on an internal
+// stream and replayed, which removes most of the per-launch host overhead of
+// small grids; the internal stream is ordered after and before the caller's
+// stream with events.
+constexpr int kGraphChunk = 16;
+
+hipError_t run_alternating(lbmrv_ctx* c, int kind_a, int kind_b, void* p, void* q, int64_t count, int mode,
+                           double alpha, const float* field, hipStream_t st) {
+  int dev = -1;
+  bool use = c->graphs_on && count >= kGraphChunk && hipGetDevice(&dev) == hipSuccess &&
+             (c->graph_dev < 0 || c->graph_dev == dev);
+  if (use && !c->gstream) {
+    if (hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->gev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->gev[1], hipEventDisableTiming) != hipSuccess)
+      return hipErrorUnknown;
+    c->graph_dev = dev;
+  }
+  if (!use) {
+    for (int64_t i = 0; i < count; ++i) {
+      const bool even = i % 2 == 0;
+      hipError_t e = run_kind(c, even ? kind_a : kind_b, even ? p : q, even ? q : p, mode, alpha, field, st);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  hipGraphExec_t exec = nullptr;
+  for (auto& g : c->graphs)
+    if (g.kind_a == kind_a && g.kind_b == kind_b && g.p == p && g.q == q && g.mode == mode &&
+        g.alpha == alpha && g.field == field && g.version == c->version)
+      exec = g.exec;
+  hipError_t e;
+  if (!exec) {
+    if ((e = hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+    hipError_t le = hipSuccess;
+    for (int i = 0; i < kGraphChunk && le == hipSuccess; ++i) {
+      const bool even = i % 2 == 0;
+      le = run_kind(c, even ? kind_a : kind_b, even ? p : q, even ? q : p, mode, alpha, field, c->gstream);
+    }
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(c->gstream, &graph);
+    if (le != hipSuccess) e = le;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return e;
+    if (c->graphs.size() >= 8) {  // keep a few entries
+      (void)hipGraphExecDestroy(c->graphs.front().exec);
+      c->graphs.erase(c->graphs.begin());
+    }
+    c->graphs.push_back({kind_a, kind_b, p, q, mode, alpha, field, c->version, exec});
+  }
+  if ((e = hipEventRecord(c->gev[0], st)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(c->gstream, c->gev[0], 0)) != hipSuccess) return e;
+  const int64_t reps = count / kGraphChunk;
+  for (int64_t r = 0; r < reps; ++r)
+    if ((e = hipGraphLaunch(exec, c->gstream)) != hipSuccess) return e;
+  for (int64_t i = reps * kGraphChunk; i < count; ++i) {  // remainder starts with kind_a (chunk is even)
+    const bool even = (i - reps * kGraphChunk) % 2 == 0;
+    if ((e = run_kind(c, even ? kind_a : kind_b, even ? p : q, even ? q : p, mode, alpha, field, c->gstream)) !=
+        hipSuccess)
+      return e;
+  }
+  if ((e = hipEventRecord(c->gev[1], c->gstream)) != hipSuccess) return e;
+  return hipStreamWaitEvent(st, c->gev[1], 0);
+}
+
 }  // namespace
 
 extern "C" {
@@ -221,6 +308,7 @@ int lbmrv_set_rates(lbmrv_ctx* c, const double* s) {
   int rc = check_rates(c->q, c->d, s);
   if (rc) return rc;
   for (int k = 0; k < c->q; ++k) c->s[k] = s[k];
+  ++c->version;
   return LBMRV_OK;
 }
 
@@ -234,6 +322,13 @@ int lbmrv_set_streaming(lbmrv_ctx* c, int kind) {
 int lbmrv_set_equilibrium(lbmrv_ctx* c, int kind) {
   if (!c || (kind != LBMRV_EQ_POLYNOMIAL && kind != LBMRV_EQ_MAXWELLIAN)) return LBMRV_ERR_INVALID_ARG;
   c->equilibrium = kind;
+  ++c->version;
+  return LBMRV_OK;
+}
+
+int lbmrv_set_graphs(lbmrv_ctx* c, int enable) {
+  if (!c) return LBMRV_ERR_INVALID_ARG;
+  c->graphs_on = enable ? 1 : 0;
   return LBMRV_OK;
 }
 
@@ -252,6 +347,7 @@ int lbmrv_set_walls(lbmrv_ctx* c, uint32_t wall_mask, const double* wall_u, doub
   for (int f = 0; f < 6; ++f)
     for (int ax = 0; ax < 3; ++ax) c->wall_u[f][ax] = u[f][ax];
   c->rho_w = rho_w;
+  ++c->version;
   return LBMRV_OK;
 }
 
@@ -283,11 +379,8 @@ int lbmrv_step(lbmrv_ctx* c, void* f_in, void* f_out, int ut_mode, double ut_alp
     if (f_in != f_out &&
         hipMemcpyAsync(f_out, f_in, eb * c->q * c->N, hipMemcpyDeviceToDevice, st) != hipSuccess)
       return LBMRV_ERR_HIP;
-    hipError_t e = hipSuccess;
-    for (int64_t t = 0; t < nsteps; ++t) {
-      e = run_kind(c, (t % 2 == 0) ? K_AA_EVEN : K_AA_ODD, f_out, f_out, ut_mode, ut_alpha, ut_field, st);
-      if (e != hipSuccess) return LBMRV_ERR_HIP;
-    }
+    hipError_t e = run_alternating(c, K_AA_EVEN, K_AA_ODD, f_out, f_out, nsteps, ut_mode, ut_alpha, ut_field, st);
+    if (e != hipSuccess) return LBMRV_ERR_HIP;
     if (nsteps % 2 == 1) e = kEntries[c->entry].fin[c->sk](f_out, c->nx, c->ny, c->nz, c->N, st);
     return e == hipSuccess ? LBMRV_OK : LBMRV_ERR_HIP;
   }
@@ -311,13 +404,9 @@ int lbmrv_step(lbmrv_ctx* c, void* f_in, void* f_out, int ut_mode, double ut_alp
       if (e != hipSuccess) return LBMRV_ERR_HIP;
       i0 = 1;
     }
-    for (int64_t i = i0; i < nsteps; ++i) {
-      void* nxt = (cur == f_in) ? f_out : f_in;
-      e = run_kind(c, K_PUSH, cur, nxt, ut_mode, ut_alpha, ut_field, st);
-      if (e != hipSuccess) return LBMRV_ERR_HIP;
-      cur = nxt;
-    }
-    return LBMRV_OK;
+    e = run_alternating(c, K_PUSH, K_PUSH, cur, cur == f_in ? f_out : f_in, nsteps - i0, ut_mode, ut_alpha,
+                        ut_field, st);
+    return e == hipSuccess ? LBMRV_OK : LBMRV_ERR_HIP;
   }
   // Pull: collide once at the start, then nsteps - 1 fused transport+collide
   // passes, then one transport.  The out-of-place passes alternate buffers and
@@ -332,12 +421,10 @@ int lbmrv_step(lbmrv_ctx* c, void* f_in, void* f_out, int ut_mode, double ut_alp
     cur = f_out;
   }
   if (e != hipSuccess) return LBMRV_ERR_HIP;
-  for (int64_t i = 1; i < nsteps; ++i) {
-    void* nxt = (cur == f_in) ? f_out : f_in;
-    e = run_kind(c, K_PULL, cur, nxt, ut_mode, ut_alpha, ut_field, st);
-    if (e != hipSuccess) return LBMRV_ERR_HIP;
-    cur = nxt;
-  }
+  void* other = (cur == f_in) ? f_out : f_in;
+  e = run_alternating(c, K_PULL, K_PULL, cur, other, nsteps - 1, ut_mode, ut_alpha, ut_field, st);
+  if (e != hipSuccess) return LBMRV_ERR_HIP;
+  if ((nsteps - 1) % 2 == 1) cur = other;
   void* nxt = (cur == f_in) ? f_out : f_in;
   e = run_kind(c, K_STREAM, cur, nxt, LBMRV_UT_ZERO, 0.0, nullptr, st);
   return e == hipSuccess ? LBMRV_OK : LBMRV_ERR_HIP;
@@ -590,6 +677,10 @@ int lbmrv_adjoint(lbmrv_ctx* c, const void* f0, int ut_mode, double ut_alpha, co
 
 void lbmrv_destroy(lbmrv_ctx* c) {
   if (!c) return;
+  for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+  if (c->gstream) (void)hipStreamDestroy(c->gstream);
+  for (auto& ev : c->gev)
+    if (ev) (void)hipEventDestroy(ev);
   if (c->partial) (void)hipFree(c->partial);
   delete c;
 }

@@ -32,6 +32,7 @@ _SIGS = {
     "lbmrv_set_streaming": (_c_int, [_c_void_p, _c_int]),
     "lbmrv_set_walls": (_c_int, [_c_void_p, ctypes.c_uint32, ctypes.POINTER(_c_double), _c_double]),
     "lbmrv_set_equilibrium": (_c_int, [_c_void_p, _c_int]),
+    "lbmrv_set_graphs": (_c_int, [_c_void_p, _c_int]),
     "lbmrv_info": (_c_int, [_c_void_p] + [ctypes.POINTER(_c_int64)] * 4),
     "lbmrv_step": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_int, _c_double, _c_void_p, _c_int64, _c_void_p]),
     "lbmrv_collide": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_int, _c_double, _c_void_p, _c_void_p]),
@@ -159,6 +160,9 @@ class Lbmrv:
 
     def set_streaming(self, kind):
         _check(library().lbmrv_set_streaming(self._h, STREAMING[kind]), "lbmrv_set_streaming")
+
+    def set_graphs(self, enable):
+        _check(library().lbmrv_set_graphs(self._h, 1 if enable else 0), "lbmrv_set_graphs")
 
     def set_equilibrium(self, kind):
         _check(library().lbmrv_set_equilibrium(self._h, EQUILIBRIA[kind]), "lbmrv_set_equilibrium")

@@ -1,0 +1,62 @@
+"""Grid-refinement study of the relative velocity's effect on the GPU (FP64).
+
+A shear wave u_y = U sin(2 pi x) advected at V runs for physical time 1 in
+acoustic scaling (dx = 1/L, fixed rates) with u~ = 0 and u~ = u.  The schemes
+share their equivalent equations up to second order (Cor. th:coreqo2), so the
+difference of their velocity fields must fall as dx^2; the GPU differences must
+also equal the oracle's where the oracle runs (L <= 64).
+"""
+import numpy as np
+import pytest
+
+from oracle import fast, lattices
+from oracle import scheme as A
+from paper_1312_3297_amd.lbmrv import Lbmrv
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+S = [0, 0, 0, 1.4, 1.7, 1.7, 1.2, 1.2, 1.4]
+U, V = 0.05, 0.1
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _state(lat, L):
+    x = np.arange(L)
+    u = np.zeros((2, L, L))
+    u[0] = V
+    u[1] = (U * np.sin(2 * np.pi * x / L))[None, :]
+    return A.equilibrium(lat, np.ones((L, L)), u)
+
+
+def _gpu_u(basis, f0, L, mode):
+    ctx = Lbmrv("d2q9", S, (L, L), "f64", basis)
+    fin = torch.from_numpy(f0).cuda()
+    fout = torch.empty_like(fin)
+    ctx.step(fin, fout, mode, 1.0, None, L)
+    _, u, _ = ctx.moments(fout)
+    torch.cuda.synchronize()
+    return u.cpu().numpy()
+
+
+@pytest.mark.parametrize("basis,name", [("default", "d2q9_paper"), ("geier", "d2q9_geier")])
+def test_relative_velocity_effect_is_second_order_in_dx(basis, name):
+    lat = lattices.make(name)
+    diffs = []
+    for L in (16, 32, 64, 128, 256):
+        f0 = _state(lat, L)
+        d = np.abs(_gpu_u(basis, f0, L, "zero") - _gpu_u(basis, f0, L, "fluid")).max() / U
+        diffs.append(d)
+        if L <= 64:
+            ua = A.conserved(lat, fast.run(lat, f0, S, L, mode=A.ZERO))[1]
+            ub = A.conserved(lat, fast.run(lat, f0, S, L, mode=A.FLUID))[1]
+            ref = np.abs(ua - ub).max() / U
+            assert abs(d - ref) <= 1e-6 * ref
+    print("\n%s: ||u(u~=0) - u(u~=u)|| / U at L = 16..256: %s" % (name, " ".join("%.3e" % d for d in diffs)))
+    for a, b in zip(diffs, diffs[1:]):
+        assert 3.6 < a / b < 4.4, diffs

@@ -468,3 +468,37 @@ def test_maxwellian_keeps_the_shear_viscosity():
         f = A.step(lat, f, s, mode=A.FLUID, eq="maxwellian")
     nu = -np.polyfit(ts, np.log(amps), 1)[0] / (2 * np.pi / L) ** 2
     assert abs(nu / ((1 / 1.7 - 0.5) / 3) - 1) < 5e-3
+
+
+# --------------------------------------------------------------------------
+# third order: u~ only enters beyond the second-order equivalent equations
+# --------------------------------------------------------------------------
+
+def _advected_shear_wave_difference(name, L, steps_per_L=1):
+    """||u(u~=0) - u(u~=u)||_inf / U after physical time 1 in acoustic scaling
+    (dx = 1/L, fixed rates): a shear wave u_y = U sin(2 pi x) advected at V."""
+    from oracle import fast
+    lat = lattices.make(name)
+    s = [0, 0, 0, 1.4, 1.7, 1.7, 1.2, 1.2, 1.4]
+    x = np.arange(L)
+    U, V = 0.05, 0.1
+    u = np.zeros((2, L, L))
+    u[0] = V
+    u[1] = (U * np.sin(2 * np.pi * x / L))[None, :]
+    f0 = A.equilibrium(lat, np.ones((L, L)), u)
+    n = steps_per_L * L
+    ua = A.conserved(lat, fast.run(lat, f0, s, n, mode=A.ZERO, threads=4))[1]
+    ub = A.conserved(lat, fast.run(lat, f0, s, n, mode=A.FLUID, threads=4))[1]
+    return np.abs(ua - ub).max() / U
+
+
+@pytest.mark.parametrize("name", ["d2q9", "d2q9_geier"])
+def test_relative_velocity_changes_the_solution_at_second_order_in_dx(name):
+    """Cor. th:coreqo2 / Prop. th:ordre3: the schemes for u~ = 0 and u~ = u share
+    their equivalent equations up to second order, so under grid refinement in
+    acoustic scaling their solutions differ by O(dx^2): halving dx divides the
+    difference by ~4."""
+    d = [_advected_shear_wave_difference(name, L) for L in (16, 32, 64)]
+    assert d[0] > 1e-4                       # the modes do differ
+    for a, b in zip(d, d[1:]):
+        assert 3.6 < a / b < 4.4, d

@@ -2,7 +2,7 @@
 
 Default workload: D3Q19, 256^3 periodic, FP32 populations, Taylor-Green vortex
 (U0 = 0.05) plus 1e-5 seeded noise, u~ = local fluid velocity (cascaded choice),
-rates bulk 1.1 / shear 1.95 / third order 1.5 / fourth order 1.8.
+rates bulk 1.1 / shear 1.95 / third order 1.5 / fourth order 1.2.
 
 A "step" is one full time step of the scheme (relaxation in the moving frame,
 then transport) over every node.  K steps are timed as one lbmrv_step call on
@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0
 # FETCH_SIZE and WRITE_SIZE counters scaled by what the same counters read for
 # a plain copy of known size (FETCH x 2.0, WRITE x 1.0); see profiles/.  Only
 # valid for the kernel version the counters were taken on.
-TRAFFIC_GB = {("d3q19_tgv256_f32_fluid", "pull"): 2.5503}
+TRAFFIC_GB = {("d3q19_tgv256_f32_fluid", "pull"): 2.5513}
 
 WORKLOADS = {
     # name: (lattice, dims, storage, mode, alpha, builder)
@@ -39,8 +39,12 @@ WORKLOADS = {
     # channel between two half-way bounce-back walls (y faces), the upper one
     # moving along x; Taylor-Green start as in the headline workload
     "d3q19_couette256_f32_fluid_walls": ("d3q19", (256, 256, 256), "f32", "fluid"),
+    # run-time moment basis (raw second moments, three normal-stress rates):
+    # the relaxation goes through a dense R^{-1} S R instead of compiled tables
+    "d3q19_tgv256_f32_fluid_rawbasis": ("d3q19", (256, 256, 256), "f32", "fluid"),
 }
 WALLS = {"d3q19_couette256_f32_fluid_walls": ((1 << 2) | (1 << 3), 0.05)}
+RUNTIME_BASIS = {"d3q19_tgv256_f32_fluid_rawbasis": ("RAW2_D3Q19", "RATES_RAW2_D3Q19")}
 
 
 def build_state(name, ctx, torch):
@@ -82,6 +86,10 @@ def cpu_baseline(name, budget_s=15.0):
     from paper_1312_3297_amd import workloads as W
     lattice, dims, storage, mode = WORKLOADS[name]
     lat = lattices.make({"d2q9": "d2q9_paper"}.get(lattice, lattice))
+    s = rates_for(lattice)
+    if name in RUNTIME_BASIS:
+        basis, rates = (getattr(W, x) for x in RUNTIME_BASIS[name])
+        lat, s = lattices.with_basis(lattice, basis), rates
     if lat.d == 3:
         sub = (32, 32, 32)
         rho, u = W.taylor_green(dims[0], 0.05, shape=sub)
@@ -90,7 +98,6 @@ def cpu_baseline(name, budget_s=15.0):
         rho, u = W.double_shear_layer(dims[0])
         rho, u = rho[: sub[0], : sub[1]], u[:, : sub[0], : sub[1]]
     f = scheme.equilibrium(lat, rho, u)
-    s = rates_for(lattice)
     smode = {"zero": scheme.ZERO, "fluid": scheme.FLUID, "field": scheme.FIELD}[mode]
     field = 0.5 * u if mode == "field" else None
     threads = min(16, os.cpu_count() or 1)
@@ -176,7 +183,12 @@ def main():
 
     name = args.workload
     lattice, dims, storage, mode = WORKLOADS[name]
-    ctx = Lbmrv(lattice, rates_for(lattice), dims, storage)
+    if name in RUNTIME_BASIS:
+        from paper_1312_3297_amd import workloads as W
+        basis, rates = (getattr(W, x) for x in RUNTIME_BASIS[name])
+        ctx = Lbmrv(lattice, rates, dims, storage, basis=basis)
+    else:
+        ctx = Lbmrv(lattice, rates_for(lattice), dims, storage)
     ctx.set_streaming(args.streaming)
     if name in WALLS:
         mask, uwall = WALLS[name]

@@ -52,8 +52,8 @@
  * element size, on the device that is current when the call is made.  A
  * `hip_stream` argument is a hipStream_t (NULL = the null stream); work is
  * enqueued on it asynchronously unless stated otherwise.  The context owns only
- * its parameters and (after the first lbmrv_conservation call) a small device
- * buffer for partial sums.
+ * its parameters, (after the first lbmrv_conservation call) a small device
+ * buffer for partial sums and, for a run-time basis, a small device table.
  *
  * Errors.  Every int-returning call returns LBMRV_OK (0) or a negative code.
  * Arguments are validated on the host before any HIP call, so an invalid call
@@ -77,7 +77,7 @@ extern "C" {
 #define LBMRV_ERR_ALIGNMENT (-6)     /* a pointer is not aligned to its element     */
 
 enum lbmrv_lattice { LBMRV_D2Q9 = 0, LBMRV_D3Q19 = 1, LBMRV_D3Q27 = 2 };
-enum lbmrv_basis { LBMRV_BASIS_DEFAULT = 0, LBMRV_BASIS_GEIER = 1 };
+enum lbmrv_basis { LBMRV_BASIS_DEFAULT = 0, LBMRV_BASIS_GEIER = 1, LBMRV_BASIS_CUSTOM = 2 };
 enum lbmrv_storage { LBMRV_F64 = 0, LBMRV_F32 = 1, LBMRV_F32DEV = 2, LBMRV_F16DEV = 3 };
 enum lbmrv_utmode { LBMRV_UT_ZERO = 0, LBMRV_UT_FLUID = 1, LBMRV_UT_FIELD = 2 };
 enum lbmrv_streaming { LBMRV_STREAM_PULL = 0, LBMRV_STREAM_PUSH = 1, LBMRV_STREAM_AA = 2 };
@@ -103,7 +103,49 @@ typedef struct lbmrv_ctx lbmrv_ctx;
 int lbmrv_create(lbmrv_ctx **out, int lattice, int basis, double lambda, const double *s,
                  const int64_t *dims, int storage, double rho0);
 
-/* Replace the q relaxation rates (same rules as lbmrv_create).  No HIP call. */
+/*
+ * A moment basis given at run time: q polynomials P_0 .. P_{q-1} in the
+ * dimensionless variable xi = X / lambda (X = v_j - u~, section 1.2), each a
+ * sum of terms coef * xi_x^ex * xi_y^ey * xi_z^ez.  Term t belongs to
+ * polynomial poly_of_term[t] and has exponents exps[3t .. 3t+2] and
+ * coefficient coef[t]; terms of one polynomial with the same exponents add up.
+ */
+typedef struct {
+  int32_t nterms;               /* number of terms, 1 .. 4096            */
+  const int32_t *poly_of_term;  /* [nterms], each in 0 .. q-1            */
+  const int32_t *exps;          /* [nterms][3], each exponent in 0 .. 8  */
+  const double *coef;           /* [nterms], finite                      */
+} lbmrv_poly_basis;
+
+/*
+ * lbmrv_create with a run-time moment basis (section 1.2 allows any
+ * polynomial basis; the rates s_k then act on its moments).  Requirements,
+ * checked on the host:
+ *   - P_0 = 1 and P_{1+a} = xi_a (a < d) exactly: the conserved moments come
+ *     first, as rho and the momentum (s_k = 0 for them, section 1.1);
+ *   - the span of P equals the span of one of the built-in bases of the
+ *     lattice (D2Q9: the span of eq. (mom) or of eq. (polgeier); D3Q19/D3Q27:
+ *     the span of the monomials listed for LBMRV_BASIS_DEFAULT), to 1e-12
+ *     relative.  These spans are closed under differentiation, so the shift
+ *     T(u~) is the exact product of Prop. th:csd2q9; in 2-D no term may
+ *     carry xi_z;
+ *   - P = R W with W that built-in basis and R well conditioned (condition
+ *     number below 1e10).
+ * The kernels shift in the built-in basis W and relax through the dense
+ * matrix R^{-1} S R of the non-conserved block, computed in FP64 on the host.
+ * The context owns a small device table (at most 19 KB) allocated on the
+ * current device by this call, filled by a blocking copy, and refreshed the
+ * same way by lbmrv_set_rates; the context must then be used on that device.
+ * lbmrv_moments returns m0_k = sum_j P_k(c_j) f_j (in xi units).  The
+ * in-place streaming form is not available (lbmrv_step returns UNSUPPORTED).
+ * Errors: INVALID_ARG (arguments, or a basis that fails a requirement above),
+ * HIP (the allocation or copy failed).
+ */
+int lbmrv_create_custom(lbmrv_ctx **out, int lattice, const lbmrv_poly_basis *basis, double lambda,
+                        const double *s, const int64_t *dims, int storage, double rho0);
+
+/* Replace the q relaxation rates (same rules as lbmrv_create).  No HIP call,
+ * except for a context with a run-time basis (see lbmrv_create_custom). */
 int lbmrv_set_rates(lbmrv_ctx *c, const double *s);
 
 /*

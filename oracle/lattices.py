@@ -135,6 +135,30 @@ class Lattice:
         return "Lattice(%s)" % self.name
 
 
+def polynomial(terms):
+    """A basis element given as terms [(coef, (a, b, c)), ...] of the monomials
+    xi_x^a xi_y^b xi_z^c in the dimensionless variable xi = X / la (section 1.2
+    allows any polynomial family; this is how a run-time basis is written)."""
+    terms = [(c, tuple(e) + (0,) * (3 - len(e))) for c, e in terms]
+
+    def P(X, Y, Z, la):
+        out = 0 * X
+        for c, (a, b, e) in terms:
+            out = out + c * (X / la) ** a * (Y / la) ** b * (Z / la) ** e
+        return out
+    return P
+
+
+def with_basis(name, polys):
+    """The velocity set and weights of lattice `name` with the moment basis
+    `polys` (q term lists, see polynomial)."""
+    import hashlib
+    base = make(name)
+    tag = hashlib.sha1(repr([[(float(c), tuple(e)) for c, e in t] for t in polys]).encode()).hexdigest()[:12]
+    return Lattice(base.name + "_custom_" + tag, base.d, [tuple(c) for c in base.c.tolist()], base.w_exact,
+                   [polynomial(t) for t in polys])
+
+
 def make(name):
     if name in ("d2q9", "d2q9_paper"):
         return Lattice("d2q9_paper", 2, D2Q9_C, D2Q9_W, D2Q9_PAPER_BASIS)

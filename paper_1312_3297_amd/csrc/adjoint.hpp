@@ -34,9 +34,11 @@ struct AdjArgs {
   uint64_t N;
   T rho0, inv_lambda, alpha;
   T s[27];
+  const T* rnn;     // run-time basis only: non-conserved block of R (P = R W), (Q-D-1)^2 row-major
+  const T* rnninv;  // and its inverse
 };
 
-template <class B, int ST, int MODE>
+template <class B, int ST, int MODE, int RLX>
 __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> a) {
   using L = typename B::Lat;
   using S = typename Store<ST>::S;
@@ -149,7 +151,27 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
   };
   if constexpr (MODE != UT_ZERO) apply_shift(v, T(-1), std::false_type{});
 
+  constexpr int NC = Q - D - 1;
+  // y = M x (or M^T x) on the non-conserved block for a run-time NC x NC matrix
+  auto dense = [&](const T* m, const T (&x)[Q], T (&y)[Q], auto transposed, auto scale_by_s) {
+    constexpr bool TR = decltype(transposed)::value;
+    constexpr bool SC = decltype(scale_by_s)::value;
+    sfor<D + 1>([&](auto kk) { y[kk] = T(0); });
+    sfor<NC>([&](auto ii) {
+      T acc = T(0);
+      sfor<NC>([&](auto jj) {
+        const T xv = SC ? x[D + 1 + jj] * a.s[D + 1 + jj] : x[D + 1 + jj];
+        acc = fmac(TR ? m[jj * NC + ii] : m[ii * NC + jj], xv, acc);
+      });
+      y[D + 1 + ii] = acc;
+    });
+  };
+
   T r[Q], am[Q];  // r = R v (user basis), am = R^{-1} S r
+  if constexpr (RLX) {
+    dense(a.rnn, v, r, std::false_type{}, std::false_type{});
+    dense(a.rnninv, r, am, std::false_type{}, std::true_type{});
+  } else {
   sfor<Q>([&](auto kk) {
     constexpr int K = kk;
     T acc = T(0);
@@ -166,6 +188,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
       });
     am[K] = acc;
   });
+  }
 
   // ---- adjoint
   T zz[Q];  // z1 -> z2 (in place through the shift)
@@ -178,7 +201,11 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
   });
   if constexpr (MODE != UT_ZERO) apply_shift(zz, T(1), std::true_type{});  // z2 = T(-u~)^T z1
 
-  T z3[Q], z5[Q];
+  T z3[Q], z5[Q];  // z3 = R^{-T} z2, z5 = R^T S z3
+  if constexpr (RLX) {
+    dense(a.rnninv, zz, z3, std::true_type{}, std::false_type{});
+    dense(a.rnn, z3, z5, std::true_type{}, std::true_type{});
+  } else {
   sfor<Q>([&](auto kk) {
     constexpr int K = kk;
     T acc = T(0);
@@ -196,6 +223,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
       });
     z5[K] = acc;
   });
+  }
 
   // dJ/du~_a = z2 . D_a am - z5 . D_a v (lattice units): accumulated per node in
   // physical units for a given field, folded into lambda for u~ = alpha u

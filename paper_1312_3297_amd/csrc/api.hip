@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <array>
 #include <new>
 #include <vector>
 
@@ -121,6 +122,12 @@ struct lbmrv_ctx {
   hipStream_t gstream = nullptr;
   hipEvent_t gev[2] = {nullptr, nullptr};
   std::vector<GraphEntry> graphs;
+  // run-time basis P = R W (W the built-in working basis of `entry`)
+  int custom = 0;
+  std::vector<double> R;              // q x q
+  std::vector<double> Rnn, Rnninv;    // non-conserved block and its inverse
+  void* dtab = nullptr;               // device: [A | R | Rnn | Rnninv] in the arithmetic type
+  int dtab_dev = -1;
 };
 
 namespace {
@@ -169,6 +176,7 @@ StepLaunch base_launch(const lbmrv_ctx* c, hipStream_t st) {
   L.eq_maxwell = c->equilibrium == LBMRV_EQ_MAXWELLIAN ? 1u : 0u;
   for (int f = 0; f < 6; ++f)
     for (int ax = 0; ax < 3; ++ax) L.wall_coef[f][ax] = 6.0 * c->rho_w * c->wall_u[f][ax] / c->lambda;
+  L.relax = c->custom ? c->dtab : nullptr;
   L.stream = st;
   L.block = c->block;
   return L;
@@ -255,6 +263,248 @@ hipError_t run_alternating(lbmrv_ctx* c, int kind_a, int kind_b, void* p, void* 
   return hipStreamWaitEvent(st, c->gev[1], 0);
 }
 
+// ---------------------------------------------------------------- run-time bases
+// Polynomials as dense coefficient vectors over a list of monomials.
+using Mono = std::array<int, 3>;
+
+int mono_index(std::vector<Mono>& keys, int a, int b, int e) {
+  for (size_t i = 0; i < keys.size(); ++i)
+    if (keys[i][0] == a && keys[i][1] == b && keys[i][2] == e) return (int)i;
+  keys.push_back({a, b, e});
+  return (int)keys.size() - 1;
+}
+
+// Terms (monomial index, coefficient) of the built-in working basis W_l.
+template <class B>
+std::vector<std::vector<std::pair<int, double>>> working_terms(std::vector<Mono>& keys) {
+  std::vector<std::vector<std::pair<int, double>>> w(B::Q);
+  for (int l = 0; l < B::Q; ++l) {
+    const Poly p = B::W(l);
+    for (int i = 0; i < p.n; ++i) w[l].push_back({mono_index(keys, p.t[i].a, p.t[i].b, p.t[i].e), p.t[i].c.val()});
+  }
+  return w;
+}
+
+// Gauss-Jordan inverse with partial pivoting of an n x n row-major matrix;
+// false if a pivot vanishes.
+bool invert(std::vector<double> a, int n, std::vector<double>& inv) {
+  inv.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (std::fabs(a[(size_t)r * n + col]) > std::fabs(a[(size_t)piv * n + col])) piv = r;
+    if (a[(size_t)piv * n + col] == 0.0) return false;
+    for (int j = 0; j < n; ++j) {
+      std::swap(a[(size_t)col * n + j], a[(size_t)piv * n + j]);
+      std::swap(inv[(size_t)col * n + j], inv[(size_t)piv * n + j]);
+    }
+    const double p = a[(size_t)col * n + col];
+    for (int j = 0; j < n; ++j) {
+      a[(size_t)col * n + j] /= p;
+      inv[(size_t)col * n + j] /= p;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      const double f = a[(size_t)r * n + col];
+      if (f == 0.0) continue;
+      for (int j = 0; j < n; ++j) {
+        a[(size_t)r * n + j] -= f * a[(size_t)col * n + j];
+        inv[(size_t)r * n + j] -= f * inv[(size_t)col * n + j];
+      }
+    }
+  }
+  return true;
+}
+
+double norm_inf(const std::vector<double>& a, int n) {
+  double m = 0.0;
+  for (int i = 0; i < n; ++i) {
+    double r = 0.0;
+    for (int j = 0; j < n; ++j) r += std::fabs(a[(size_t)i * n + j]);
+    m = r > m ? r : m;
+  }
+  return m;
+}
+
+// Express the user polynomials in the working basis W of one built-in entry:
+// P_k = sum_l R[k][l] W_l, by least squares over the monomial coefficients
+// (modified Gram-Schmidt on the columns W_l, applied twice).  Returns false
+// if some P_k is not in span(W) to 1e-12 relative.
+template <class B>
+bool express_in(const lbmrv_poly_basis* pb, std::vector<double>& R) {
+  constexpr int Q = B::Q;
+  std::vector<Mono> keys;
+  auto wt = working_terms<B>(keys);
+  std::vector<std::vector<std::pair<int, double>>> pt(Q);
+  for (int t = 0; t < pb->nterms; ++t)
+    pt[pb->poly_of_term[t]].push_back(
+        {mono_index(keys, pb->exps[3 * t], pb->exps[3 * t + 1], pb->exps[3 * t + 2]), pb->coef[t]});
+  const int nm = (int)keys.size();
+  std::vector<double> Wc((size_t)Q * nm, 0.0), Pc((size_t)Q * nm, 0.0);  // column l: coefficients of W_l
+  for (int l = 0; l < Q; ++l)
+    for (auto& [i, c] : wt[l]) Wc[(size_t)l * nm + i] += c;
+  for (int k = 0; k < Q; ++k)
+    for (auto& [i, c] : pt[k]) Pc[(size_t)k * nm + i] += c;
+  // W = Qm Rr (columns), Qm orthonormal
+  std::vector<double> Qm = Wc, Rr((size_t)Q * Q, 0.0);
+  for (int l = 0; l < Q; ++l) {
+    double* ql = &Qm[(size_t)l * nm];
+    for (int pass = 0; pass < 2; ++pass)
+      for (int m = 0; m < l; ++m) {
+        const double* qm = &Qm[(size_t)m * nm];
+        double dot = 0.0;
+        for (int i = 0; i < nm; ++i) dot += qm[i] * ql[i];
+        for (int i = 0; i < nm; ++i) ql[i] -= dot * qm[i];
+        Rr[(size_t)m * Q + l] += dot;
+      }
+    double nrm = 0.0;
+    for (int i = 0; i < nm; ++i) nrm += ql[i] * ql[i];
+    nrm = std::sqrt(nrm);
+    if (nrm == 0.0) return false;
+    for (int i = 0; i < nm; ++i) ql[i] /= nrm;
+    Rr[(size_t)l * Q + l] = nrm;
+  }
+  R.assign((size_t)Q * Q, 0.0);
+  for (int k = 0; k < Q; ++k) {
+    const double* pk = &Pc[(size_t)k * nm];
+    double y[Q], x[Q];
+    for (int l = 0; l < Q; ++l) {
+      double dot = 0.0;
+      for (int i = 0; i < nm; ++i) dot += Qm[(size_t)l * nm + i] * pk[i];
+      y[l] = dot;
+    }
+    for (int l = Q - 1; l >= 0; --l) {  // Rr x = y (upper triangular)
+      double v = y[l];
+      for (int m = l + 1; m < Q; ++m) v -= Rr[(size_t)l * Q + m] * x[m];
+      x[l] = v / Rr[(size_t)l * Q + l];
+    }
+    double res = 0.0, ref = 0.0;
+    for (int i = 0; i < nm; ++i) {
+      double v = pk[i];
+      for (int l = 0; l < Q; ++l) v -= x[l] * Wc[(size_t)l * nm + i];
+      res += v * v;
+      ref += pk[i] * pk[i];
+    }
+    if (!(std::sqrt(res) <= 1e-12 * std::sqrt(ref))) return false;
+    for (int l = 0; l < Q; ++l) R[(size_t)k * Q + l] = x[l];
+  }
+  return true;
+}
+
+// Validate a run-time basis and find the built-in entry whose working basis
+// spans it; fills R, the non-conserved block of R and its inverse.
+int analyse_basis(int lattice, const lbmrv_poly_basis* pb, int& entry, std::vector<double>& R,
+                  std::vector<double>& Rnn, std::vector<double>& Rnninv) {
+  const int q = lattice_q(lattice), d = lattice_d(lattice), nc = q - d - 1;
+  if (!pb || pb->nterms < 1 || pb->nterms > 4096 || !pb->poly_of_term || !pb->exps || !pb->coef)
+    return LBMRV_ERR_INVALID_ARG;
+  std::vector<int> seen(q, 0);
+  for (int t = 0; t < pb->nterms; ++t) {
+    const int k = pb->poly_of_term[t];
+    if (k < 0 || k >= q || !std::isfinite(pb->coef[t])) return LBMRV_ERR_INVALID_ARG;
+    for (int a = 0; a < 3; ++a)
+      if (pb->exps[3 * t + a] < 0 || pb->exps[3 * t + a] > 8) return LBMRV_ERR_INVALID_ARG;
+    if (d == 2 && pb->exps[3 * t + 2] != 0 && pb->coef[t] != 0.0) return LBMRV_ERR_INVALID_ARG;
+    seen[k] = 1;
+  }
+  for (int k = 0; k < q; ++k)
+    if (!seen[k]) return LBMRV_ERR_INVALID_ARG;
+  // the conserved polynomials, exactly: P_0 = 1, P_{1+a} = xi_a
+  for (int k = 0; k <= d; ++k) {
+    double sum[4] = {0, 0, 0, 0};  // coefficients of 1, xi_x, xi_y, xi_z
+    double other = 0.0;
+    for (int t = 0; t < pb->nterms; ++t) {
+      if (pb->poly_of_term[t] != k) continue;
+      const int* e = &pb->exps[3 * t];
+      const int deg = e[0] + e[1] + e[2];
+      if (deg == 0) sum[0] += pb->coef[t];
+      else if (deg == 1) sum[1 + (e[0] ? 0 : e[1] ? 1 : 2)] += pb->coef[t];
+      else other = std::fabs(pb->coef[t]) > other ? std::fabs(pb->coef[t]) : other;
+    }
+    for (int i = 0; i < 4; ++i)
+      if (sum[i] != (i == k ? 1.0 : 0.0)) return LBMRV_ERR_INVALID_ARG;
+    if (other != 0.0) return LBMRV_ERR_INVALID_ARG;
+  }
+  bool ok = false;
+  if (lattice == LBMRV_D2Q9) {
+    if ((ok = express_in<BasisD2Q9Paper>(pb, R))) entry = 0;
+    else if ((ok = express_in<BasisD2Q9Geier>(pb, R))) entry = 1;
+  } else if (lattice == LBMRV_D3Q19) {
+    if ((ok = express_in<BasisD3Q19>(pb, R))) entry = 2;
+  } else {
+    if ((ok = express_in<BasisD3Q27>(pb, R))) entry = 3;
+  }
+  if (!ok) return LBMRV_ERR_INVALID_ARG;
+  for (int k = 0; k <= d; ++k)
+    for (int l = 0; l < q; ++l) R[(size_t)k * q + l] = k == l ? 1.0 : 0.0;
+  Rnn.assign((size_t)nc * nc, 0.0);
+  for (int i = 0; i < nc; ++i)
+    for (int j = 0; j < nc; ++j) Rnn[(size_t)i * nc + j] = R[(size_t)(d + 1 + i) * q + d + 1 + j];
+  if (!invert(Rnn, nc, Rnninv)) return LBMRV_ERR_INVALID_ARG;
+  const double cond = norm_inf(Rnn, nc) * norm_inf(Rnninv, nc);
+  if (!(cond < 1e10)) return LBMRV_ERR_INVALID_ARG;
+  return LBMRV_OK;
+}
+
+// Fill the device table of a run-time basis: A = Rnn^{-1} S Rnn, R, Rnn,
+// Rnn^{-1}, in the arithmetic type of the storage.  Blocking; waits for the
+// device first so that no kernel still reads the previous table.
+int upload_basis(lbmrv_ctx* c) {
+  const int q = c->q, d = c->d, nc = q - d - 1;
+  std::vector<double> tab;
+  tab.reserve((size_t)3 * nc * nc + (size_t)q * q);
+  for (int i = 0; i < nc; ++i)
+    for (int j = 0; j < nc; ++j) {
+      double a = 0.0;
+      for (int k = 0; k < nc; ++k) a += c->Rnninv[(size_t)i * nc + k] * c->s[d + 1 + k] * c->Rnn[(size_t)k * nc + j];
+      tab.push_back(a);
+    }
+  tab.insert(tab.end(), c->R.begin(), c->R.end());
+  tab.insert(tab.end(), c->Rnn.begin(), c->Rnn.end());
+  tab.insert(tab.end(), c->Rnninv.begin(), c->Rnninv.end());
+  const bool f64 = c->storage == LBMRV_F64;
+  const size_t bytes = tab.size() * (f64 ? 8 : 4);
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return LBMRV_ERR_HIP;
+  if (c->dtab && dev != c->dtab_dev) return LBMRV_ERR_INVALID_ARG;
+  if (!c->dtab) {
+    if (hipMalloc(&c->dtab, bytes) != hipSuccess) {
+      c->dtab = nullptr;
+      return LBMRV_ERR_HIP;
+    }
+    c->dtab_dev = dev;
+  }
+  if (hipDeviceSynchronize() != hipSuccess) return LBMRV_ERR_HIP;
+  hipError_t e;
+  if (f64) {
+    e = hipMemcpy(c->dtab, tab.data(), bytes, hipMemcpyHostToDevice);
+  } else {
+    std::vector<float> t32(tab.begin(), tab.end());
+    e = hipMemcpy(c->dtab, t32.data(), bytes, hipMemcpyHostToDevice);
+  }
+  return e == hipSuccess ? LBMRV_OK : LBMRV_ERR_HIP;
+}
+
+// Byte offsets of the tables inside dtab.
+size_t tab_offset(const lbmrv_ctx* c, int which) {  // 0 A, 1 R, 2 Rnn, 3 Rnninv
+  const size_t nc = (size_t)(c->q - c->d - 1), q = (size_t)c->q, eb = c->storage == LBMRV_F64 ? 8 : 4;
+  const size_t off[4] = {0, nc * nc, nc * nc + q * q, 2 * nc * nc + q * q};
+  return off[which] * eb;
+}
+
+const void* tab_ptr(const lbmrv_ctx* c, int which) {
+  return c->custom ? static_cast<const char*>(c->dtab) + tab_offset(c, which) : nullptr;
+}
+
+// A context with a run-time basis must be used on the device its table lives on.
+int check_device(const lbmrv_ctx* c) {
+  if (!c->custom) return LBMRV_OK;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return LBMRV_ERR_HIP;
+  return dev == c->dtab_dev ? LBMRV_OK : LBMRV_ERR_INVALID_ARG;
+}
+
 }  // namespace
 
 extern "C" {
@@ -303,13 +553,40 @@ int lbmrv_create(lbmrv_ctx** out, int lattice, int basis, double lambda, const d
   return LBMRV_OK;
 }
 
+int lbmrv_create_custom(lbmrv_ctx** out, int lattice, const lbmrv_poly_basis* basis, double lambda, const double* s,
+                        const int64_t* dims, int storage, double rho0) {
+  if (!out) return LBMRV_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (lattice != LBMRV_D2Q9 && lattice != LBMRV_D3Q19 && lattice != LBMRV_D3Q27) return LBMRV_ERR_INVALID_ARG;
+  int entry = -1;
+  std::vector<double> R, Rnn, Rnninv;
+  int rc = analyse_basis(lattice, basis, entry, R, Rnn, Rnninv);
+  if (rc) return rc;
+  lbmrv_ctx* c = nullptr;
+  if ((rc = lbmrv_create(&c, lattice, entry == 1 ? LBMRV_BASIS_GEIER : LBMRV_BASIS_DEFAULT, lambda, s, dims, storage,
+                         rho0)))
+    return rc;
+  c->basis = LBMRV_BASIS_CUSTOM;
+  c->custom = 1;
+  c->R = std::move(R);
+  c->Rnn = std::move(Rnn);
+  c->Rnninv = std::move(Rnninv);
+  if ((rc = upload_basis(c))) {
+    lbmrv_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return LBMRV_OK;
+}
+
 int lbmrv_set_rates(lbmrv_ctx* c, const double* s) {
   if (!c) return LBMRV_ERR_INVALID_ARG;
   int rc = check_rates(c->q, c->d, s);
   if (rc) return rc;
+  if ((rc = check_device(c))) return rc;
   for (int k = 0; k < c->q; ++k) c->s[k] = s[k];
   ++c->version;
-  return LBMRV_OK;
+  return c->custom ? upload_basis(c) : LBMRV_OK;
 }
 
 int lbmrv_set_streaming(lbmrv_ctx* c, int kind) {
@@ -370,6 +647,8 @@ int lbmrv_step(lbmrv_ctx* c, void* f_in, void* f_out, int ut_mode, double ut_alp
   if (f_in == f_out && c->streaming != LBMRV_STREAM_AA) return LBMRV_ERR_INVALID_ARG;
   if ((rc = check_mode(c, ut_mode, ut_alpha, ut_field))) return rc;
   if (c->wall_mask && c->streaming != LBMRV_STREAM_PULL) return LBMRV_ERR_UNSUPPORTED;
+  if (c->custom && c->streaming == LBMRV_STREAM_AA) return LBMRV_ERR_UNSUPPORTED;
+  if ((rc = check_device(c))) return rc;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   if (c->streaming == LBMRV_STREAM_AA) {
     // One array, in place: even steps collide at the node and store each
@@ -437,6 +716,7 @@ int lbmrv_collide(lbmrv_ctx* c, const void* f_in, void* f_out, int ut_mode, doub
   int rc;
   if ((rc = check_ptr(f_in, eb)) || (rc = check_ptr(f_out, eb))) return rc;
   if ((rc = check_mode(c, ut_mode, ut_alpha, ut_field))) return rc;
+  if ((rc = check_device(c))) return rc;
   hipError_t e = run_kind(c, K_COLLIDE, f_in, f_out, ut_mode, ut_alpha, ut_field, static_cast<hipStream_t>(hip_stream));
   return e == hipSuccess ? LBMRV_OK : LBMRV_ERR_HIP;
 }
@@ -458,6 +738,7 @@ int lbmrv_moments(lbmrv_ctx* c, const void* f, void* rho, void* u, void* m0, voi
   int rc;
   if ((rc = check_ptr(f, eb)) || (rc = check_ptr(rho, ob)) || (rc = check_ptr(u, ob))) return rc;
   if (m0 && (rc = check_ptr(m0, ob))) return rc;
+  if ((rc = check_device(c))) return rc;
   MomLaunch L{};
   L.sk = c->sk;
   L.f = f;
@@ -467,6 +748,7 @@ int lbmrv_moments(lbmrv_ctx* c, const void* f, void* rho, void* u, void* m0, voi
   L.N = c->N;
   L.rho0 = c->rho0;
   L.lambda = c->lambda;
+  L.rmat = tab_ptr(c, 1);
   L.stream = static_cast<hipStream_t>(hip_stream);
   return kEntries[c->entry].mom[c->sk](L) == hipSuccess ? LBMRV_OK : LBMRV_ERR_HIP;
 }
@@ -610,6 +892,7 @@ int lbmrv_adjoint(lbmrv_ctx* c, const void* f0, int ut_mode, double ut_alpha, co
     return rc;
   if (f_N && (rc = check_ptr(f_N, eb))) return rc;
   if (ut_mode == LBMRV_UT_FIELD && ((rc = check_ptr(ut_field, 4)) || (rc = check_ptr(grad_ut, 8)))) return rc;
+  if ((rc = check_device(c))) return rc;
   const AdjPlan P = adj_plan(c, nsteps, K);
   if (workspace_bytes < P.total) return LBMRV_ERR_INVALID_ARG;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
@@ -651,6 +934,8 @@ int lbmrv_adjoint(lbmrv_ctx* c, const void* f0, int ut_mode, double ut_alpha, co
   A.inv_lambda = 1.0 / c->lambda;
   A.alpha = ut_alpha;
   for (int k = 0; k < 27; ++k) A.s[k] = k < c->q ? c->s[k] : 0.0;
+  A.rnn = tab_ptr(c, 2);
+  A.rnninv = tab_ptr(c, 3);
   A.stream = st;
   A.block = c->block;
   // reverse sweep, one segment of K steps at a time; the last segment's states
@@ -682,6 +967,7 @@ void lbmrv_destroy(lbmrv_ctx* c) {
   for (auto& ev : c->gev)
     if (ev) (void)hipEventDestroy(ev);
   if (c->partial) (void)hipFree(c->partial);
+  if (c->dtab) (void)hipFree(c->dtab);
   delete c;
 }
 

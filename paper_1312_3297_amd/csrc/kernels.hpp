@@ -81,12 +81,17 @@ struct StepArgs {
   uint32_t wall_mask;  // bit 2a+side: the low (0) / high (1) face of axis a is a wall
   T wall_coef[6][3];   // 6 rho_w u_w / lambda per wall face (half-way bounce-back)
   uint32_t eq_maxwell; // 1: equilibrium moments of the continuous Maxwellian
+  const T* relax;      // run-time basis only: the non-conserved block of R^{-1} S R,
+                       // (Q-D-1)^2 row-major, in the working basis
 };
 
 // ------------------------------------------------------------------ collision
 // In-register collision at one node.  h holds the populations minus w_j rho0.
 // After return h holds the post-collision values (same offset).
-template <class B, class T, int MODE>
+// RLX = 0: rates act on the built-in user basis (sparse compile-time R);
+// RLX = 1: on a run-time basis P = R W of the same span, through the dense
+// matrix a.relax = R^{-1} S R (non-conserved block).
+template <class B, class T, int MODE, int RLX>
 __device__ __forceinline__ void collide_node(T (&h)[B::Q], const StepArgs<T>& a, const T (&utf)[3]) {
   using L = typename B::Lat;
   constexpr int Q = B::Q;
@@ -211,7 +216,16 @@ __device__ __forceinline__ void collide_node(T (&h)[B::Q], const StepArgs<T>& a,
   if constexpr (MODE != UT_ZERO) shift(T(-1));
 
   // diagonal relaxation in the user basis, eq. (relaxationu): r = Rinv S R dl
-  {
+  if constexpr (RLX) {
+    constexpr int NC = Q - D - 1;
+    T r[NC];
+    sfor<NC>([&](auto ii) {
+      T acc = T(0);
+      sfor<NC>([&](auto jj) { acc = fmac(a.relax[ii * NC + jj], dl[D + 1 + jj], acc); });
+      r[ii] = acc;
+    });
+    sfor<NC>([&](auto ii) { dl[D + 1 + ii] = r[ii]; });
+  } else {
     T r[Q];
     sfor<Q>([&](auto kk) {
       constexpr int K = kk;
@@ -256,7 +270,7 @@ constexpr int step_max_threads() {
   return ST == 0 ? 512 : 1024;
 }
 
-template <class B, int ST, int MODE, int KIND>
+template <class B, int ST, int MODE, int KIND, int RLX>
 __global__ __launch_bounds__(step_max_threads<ST>()) void k_step(StepArgs<typename Store<ST>::T> a) {
   using L = typename B::Lat;
   using S = typename Store<ST>::S;
@@ -341,7 +355,7 @@ __global__ __launch_bounds__(step_max_threads<ST>()) void k_step(StepArgs<typena
     if constexpr (MODE == UT_FIELD) {
       sfor<D>([&](auto al) { utf[al] = T(a.ut[(uint64_t)al * N + own]) * a.inv_lambda; });
     }
-    collide_node<B, T, MODE>(h, a, utf);
+    collide_node<B, T, MODE, RLX>(h, a, utf);
   }
 
   // Stores: the gather forms write their own node (aligned, contiguous per
@@ -400,6 +414,7 @@ struct MomArgs {
   void* m0;    // [q][N] or null
   uint64_t N;
   T rho0, lambda;
+  const T* rmat;  // run-time basis only: R of P = R W, Q x Q row-major (m0 then in xi = X / lambda units)
 };
 
 // rho, u (physical units) and optionally the fixed-frame user moments
@@ -430,7 +445,28 @@ __global__ __launch_bounds__(256) void k_moments(MomArgs<typename Store<ST>::T> 
   const T rho = a.rho0 + drho;
   static_cast<O*>(a.rho)[n] = O(rho);
   sfor<D>([&](auto al) { static_cast<O*>(a.u)[(uint64_t)al * a.N + n] = O(a.lambda * jm[al] / rho); });
-  if (a.m0) {
+  if (a.m0 && a.rmat) {
+    // run-time basis: m0 = R M_W(0) f
+    T mw[Q];
+    sfor<Q>([&](auto kk) {
+      constexpr int K = kk;
+      T acc = T(0);
+      sfor<Tb::t.sMW[K].n>([&](auto i) { axpy_c<Tb::t.sMW[K].val[i]>(acc, h[Tb::t.sMW[K].col[i]]); });
+      constexpr Rat restK = [] {
+        Rat r;
+        for (int j = 0; j < Q; ++j) r = r + Tb::t.MW.m[K][j] * Tb::t.w[j];
+        return r;
+      }();
+      if constexpr (!restK.zero()) acc = fmac(lit<restK, T>(), a.rho0, acc);
+      mw[K] = acc;
+    });
+    sfor<Q>([&](auto kk) {
+      constexpr int K = kk;
+      T acc = T(0);
+      sfor<Q>([&](auto ll) { acc = fmac(a.rmat[K * Q + ll], mw[ll], acc); });
+      static_cast<O*>(a.m0)[(uint64_t)K * a.N + n] = O(acc);
+    });
+  } else if (a.m0) {
     sfor<Q>([&](auto kk) {
       constexpr int K = kk;
       T acc = T(0);

@@ -27,6 +27,7 @@ struct StepLaunch {
   uint32_t wall_mask;
   double wall_coef[6][3];
   uint32_t eq_maxwell;
+  const void* relax;  // run-time basis: R^{-1} S R block in the arithmetic type, or null
   hipStream_t stream;
   int block;   // threads per block along x
 };
@@ -39,10 +40,11 @@ struct MomLaunch {
   void* m0;
   uint64_t N;
   double rho0, lambda;
+  const void* rmat;  // run-time basis: R (Q x Q) in the arithmetic type, or null
   hipStream_t stream;
 };
 
-template <class B, int ST, int MODE, int KIND>
+template <class B, int ST, int MODE, int KIND, int RLX>
 hipError_t launch_step_t(const StepLaunch& L) {
   using T = typename Store<ST>::T;
   StepArgs<T> a{};
@@ -59,6 +61,7 @@ hipError_t launch_step_t(const StepLaunch& L) {
   for (int k = 0; k < 27; ++k) a.s[k] = T(L.s[k]);
   a.wall_mask = L.wall_mask;
   a.eq_maxwell = L.eq_maxwell;
+  a.relax = static_cast<const T*>(L.relax);
   for (int f = 0; f < 6; ++f)
     for (int ax = 0; ax < 3; ++ax) a.wall_coef[f][ax] = T(L.wall_coef[f][ax]);
   // block: whole wavefronts along x (at most 256 threads), and for the gather
@@ -68,19 +71,28 @@ hipError_t launch_step_t(const StepLaunch& L) {
   uint32_t by = (KIND == K_PUSH || KIND == K_AA_ODD || ST == 2) ? 1u : (uint32_t)step_max_threads<ST>() / bx;
   if (by > L.ny) by = L.ny;
   dim3 grid((L.nx + bx - 1) / bx, (L.ny + by - 1) / by, L.nz);
-  hipLaunchKernelGGL((k_step<B, ST, MODE, KIND>), grid, dim3(bx, by), 0, L.stream, a);
+  hipLaunchKernelGGL((k_step<B, ST, MODE, KIND, RLX>), grid, dim3(bx, by), 0, L.stream, a);
   return hipGetLastError();
 }
 
 template <class B, int ST, int MODE>
 hipError_t launch_step_m(const StepLaunch& L) {
+  if (L.relax) {  // run-time basis: the two-array forms
+    switch (L.kind) {
+      case K_PULL: return launch_step_t<B, ST, MODE, K_PULL, 1>(L);
+      case K_PUSH: return launch_step_t<B, ST, MODE, K_PUSH, 1>(L);
+      case K_COLLIDE: return launch_step_t<B, ST, MODE, K_COLLIDE, 1>(L);
+      case K_STREAM: return launch_step_t<B, ST, UT_ZERO, K_STREAM, 0>(L);
+    }
+    return hipErrorInvalidValue;
+  }
   switch (L.kind) {
-    case K_PULL: return launch_step_t<B, ST, MODE, K_PULL>(L);
-    case K_PUSH: return launch_step_t<B, ST, MODE, K_PUSH>(L);
-    case K_COLLIDE: return launch_step_t<B, ST, MODE, K_COLLIDE>(L);
-    case K_STREAM: return launch_step_t<B, ST, UT_ZERO, K_STREAM>(L);
-    case K_AA_EVEN: return launch_step_t<B, ST, MODE, K_AA_EVEN>(L);
-    case K_AA_ODD: return launch_step_t<B, ST, MODE, K_AA_ODD>(L);
+    case K_PULL: return launch_step_t<B, ST, MODE, K_PULL, 0>(L);
+    case K_PUSH: return launch_step_t<B, ST, MODE, K_PUSH, 0>(L);
+    case K_COLLIDE: return launch_step_t<B, ST, MODE, K_COLLIDE, 0>(L);
+    case K_STREAM: return launch_step_t<B, ST, UT_ZERO, K_STREAM, 0>(L);
+    case K_AA_EVEN: return launch_step_t<B, ST, MODE, K_AA_EVEN, 0>(L);
+    case K_AA_ODD: return launch_step_t<B, ST, MODE, K_AA_ODD, 0>(L);
   }
   return hipErrorInvalidValue;
 }
@@ -113,6 +125,7 @@ hipError_t launch_moments_t(const MomLaunch& L) {
   a.N = L.N;
   a.rho0 = T(L.rho0);
   a.lambda = T(L.lambda);
+  a.rmat = static_cast<const T*>(L.rmat);
   const unsigned grid = (unsigned)((L.N + 255) / 256);
   hipLaunchKernelGGL((k_moments<B, ST>), dim3(grid), dim3(256), 0, L.stream, a);
   return hipGetLastError();
@@ -161,11 +174,13 @@ struct AdjLaunch {
   uint64_t N;
   double rho0, inv_lambda, alpha;
   double s[27];
+  const void* rnn;     // run-time basis: non-conserved block of R and its inverse, or null
+  const void* rnninv;
   hipStream_t stream;
   int block;
 };
 
-template <class B, int ST, int MODE>
+template <class B, int ST, int MODE, int RLX>
 hipError_t launch_adjoint_t(const AdjLaunch& L) {
   using T = typename Store<ST>::T;
   AdjArgs<T> a{};
@@ -183,18 +198,25 @@ hipError_t launch_adjoint_t(const AdjLaunch& L) {
   a.inv_lambda = T(L.inv_lambda);
   a.alpha = T(L.alpha);
   for (int k = 0; k < 27; ++k) a.s[k] = T(L.s[k]);
+  a.rnn = static_cast<const T*>(L.rnn);
+  a.rnninv = static_cast<const T*>(L.rnninv);
   const int bx = L.block;
   dim3 grid((L.nx + bx - 1) / bx, L.ny, L.nz);
-  hipLaunchKernelGGL((k_adjoint<B, ST, MODE>), grid, dim3(bx), 0, L.stream, a);
+  hipLaunchKernelGGL((k_adjoint<B, ST, MODE, RLX>), grid, dim3(bx), 0, L.stream, a);
   return hipGetLastError();
+}
+
+template <class B, int ST, int RLX>
+hipError_t launch_adjoint_r(const AdjLaunch& L) {
+  if (L.mode == UT_ZERO) return launch_adjoint_t<B, ST, UT_ZERO, RLX>(L);
+  if (L.mode == UT_FLUID) return launch_adjoint_t<B, ST, UT_FLUID, RLX>(L);
+  if (L.mode == UT_FIELD) return launch_adjoint_t<B, ST, UT_FIELD, RLX>(L);
+  return hipErrorInvalidValue;
 }
 
 template <class B, int ST>
 hipError_t launch_adjoint_s(const AdjLaunch& L) {
-  if (L.mode == UT_ZERO) return launch_adjoint_t<B, ST, UT_ZERO>(L);
-  if (L.mode == UT_FLUID) return launch_adjoint_t<B, ST, UT_FLUID>(L);
-  if (L.mode == UT_FIELD) return launch_adjoint_t<B, ST, UT_FIELD>(L);
-  return hipErrorInvalidValue;
+  return L.rnn ? launch_adjoint_r<B, ST, 1>(L) : launch_adjoint_r<B, ST, 0>(L);
 }
 
 // Per-(lattice, basis, storage) entry points, defined in the lattice translation

@@ -25,9 +25,17 @@ _c_int = ctypes.c_int
 _c_double = ctypes.c_double
 _c_int64 = ctypes.c_int64
 
+class PolyBasis(ctypes.Structure):
+    """lbmrv_poly_basis: q polynomials in xi = X / lambda as a list of terms."""
+    _fields_ = [("nterms", ctypes.c_int32), ("poly_of_term", ctypes.POINTER(ctypes.c_int32)),
+                ("exps", ctypes.POINTER(ctypes.c_int32)), ("coef", ctypes.POINTER(_c_double))]
+
+
 _SIGS = {
     "lbmrv_create": (_c_int, [ctypes.POINTER(_c_void_p), _c_int, _c_int, _c_double, ctypes.POINTER(_c_double),
                               ctypes.POINTER(_c_int64), _c_int, _c_double]),
+    "lbmrv_create_custom": (_c_int, [ctypes.POINTER(_c_void_p), _c_int, ctypes.POINTER(PolyBasis), _c_double,
+                                     ctypes.POINTER(_c_double), ctypes.POINTER(_c_int64), _c_int, _c_double]),
     "lbmrv_set_rates": (_c_int, [_c_void_p, ctypes.POINTER(_c_double)]),
     "lbmrv_set_streaming": (_c_int, [_c_void_p, _c_int]),
     "lbmrv_set_walls": (_c_int, [_c_void_p, ctypes.c_uint32, ctypes.POINTER(_c_double), _c_double]),
@@ -102,8 +110,31 @@ def lattice_tables(lattice):
     return np.array(c[:], dtype=np.int64).reshape(q, 3), np.array(w[:])
 
 
+def poly_basis(polys):
+    """Marshal q polynomials, each a list of (coef, (ex, ey, ez)) terms, into a
+    PolyBasis; the ctypes arrays are kept alive on the returned object."""
+    pot, exps, coef = [], [], []
+    for k, terms in enumerate(polys):
+        for c, e in terms:
+            e = tuple(int(x) for x in e) + (0,) * (3 - len(e))
+            pot.append(k)
+            exps.extend(e)
+            coef.append(float(c))
+    n = len(pot)
+    arrs = ((ctypes.c_int32 * max(n, 1))(*pot), (ctypes.c_int32 * max(3 * n, 1))(*exps),
+            (_c_double * max(n, 1))(*coef))
+    pb = PolyBasis(n, ctypes.cast(arrs[0], ctypes.POINTER(ctypes.c_int32)),
+                   ctypes.cast(arrs[1], ctypes.POINTER(ctypes.c_int32)), ctypes.cast(arrs[2], ctypes.POINTER(_c_double)))
+    pb._keep = arrs
+    return pb
+
+
 class Lbmrv:
-    """One context: lattice, basis, lambda, rates, grid (nx, ny[, nz]) and storage."""
+    """One context: lattice, basis, lambda, rates, grid (nx, ny[, nz]) and storage.
+
+    basis is "default", "geier" (D2Q9) or a run-time basis: a sequence of q
+    polynomials in xi = X / lambda, each a list of (coef, (ex, ey, ez)) terms
+    (see lbmrv_create_custom for the requirements)."""
 
     def __init__(self, lattice, s, dims, storage="f32", basis="default", lam=1.0, rho0=1.0):
         self.lattice, self.basis, self.storage = lattice, basis, storage
@@ -116,8 +147,13 @@ class Lbmrv:
         rates = (_c_double * self.q)(*[float(x) for x in s])
         dd = (_c_int64 * 3)(*(list(self.dims) + [1] * (3 - self.d)))
         h = _c_void_p()
-        _check(library().lbmrv_create(ctypes.byref(h), LATTICES[lattice], BASES[basis], self.lam, rates, dd,
-                                      STORAGES[storage], self.rho0), "lbmrv_create")
+        if isinstance(basis, str):
+            _check(library().lbmrv_create(ctypes.byref(h), LATTICES[lattice], BASES[basis], self.lam, rates, dd,
+                                          STORAGES[storage], self.rho0), "lbmrv_create")
+        else:
+            pb = poly_basis(basis)
+            _check(library().lbmrv_create_custom(ctypes.byref(h), LATTICES[lattice], ctypes.byref(pb), self.lam,
+                                                 rates, dd, STORAGES[storage], self.rho0), "lbmrv_create_custom")
         self._h = h
         self.N = int(np.prod(self.dims))
 

@@ -87,3 +87,53 @@ RATES_D2Q9_SHEAR_LAYER = [0, 0, 0, 1.2, 1.9, 1.9, 1.5, 1.5, 1.8]
 # runs blow up within ~60 steps, in the oracle as well as on the GPU)
 RATES_D3Q19 = [0.0] * 4 + [1.1] + [1.95] * 5 + [1.5] * 6 + [1.2] * 3
 RATES_D3Q27 = [0.0] * 4 + [1.1] + [1.95] * 5 + [1.5] * 7 + [1.2] * 10
+
+
+# ---------------------------------------------------------------------------
+# run-time moment bases (q polynomials in xi = X / lambda, as (coef, exponents)
+# terms) and rates for them
+# ---------------------------------------------------------------------------
+def _t(c, a=0, b=0, e=0):
+    return (c, (a, b, e))
+
+
+def _herm(a, b, e):
+    """Tensor Hermite-like polynomial H_a(xi_x) H_b(xi_y) H_c(xi_z) with
+    H_0 = 1, H_1 = xi, H_2 = xi^2 - 1/3, expanded into monomial terms."""
+    per_axis = {0: [(1.0, 0)], 1: [(1.0, 1)], 2: [(1.0, 2), (-1.0 / 3.0, 0)]}
+    out = []
+    for ca, pa in per_axis[a]:
+        for cb, pb in per_axis[b]:
+            for ce, pe in per_axis[e]:
+                out.append(_t(ca * cb * ce, pa, pb, pe))
+    return out
+
+
+# D2Q9, Geier's span: Hermite-like family (constants mixed into the second- and
+# fourth-order elements, and xi^2 terms into the fourth-order one)
+HERMITE_D2Q9 = [_herm(0, 0, 0), _herm(1, 0, 0), _herm(0, 1, 0),
+                [_t(1, 2), _t(1, 0, 2), _t(-2.0 / 3.0)], [_t(1, 2), _t(-1, 0, 2)], _herm(1, 1, 0),
+                _herm(1, 2, 0), _herm(2, 1, 0), _herm(2, 2, 0)]
+RATES_HERMITE_D2Q9 = [0, 0, 0, 1.1, 1.6, 1.75, 1.3, 1.45, 1.9]
+
+# D2Q9, the span of eq. (mom): raw powers of |xi|^2 instead of the orthogonal family
+RAW_D2Q9 = [[_t(1)], [_t(1, 1)], [_t(1, 0, 1)], [_t(1, 2), _t(1, 0, 2)], [_t(1, 2), _t(-1, 0, 2)], [_t(1, 1, 1)],
+            [_t(1, 3), _t(1, 1, 2)], [_t(1, 2, 1), _t(1, 0, 3)], [_t(1, 4), _t(2, 2, 2), _t(1, 0, 4)]]
+RATES_RAW_D2Q9 = [0, 0, 0, 1.2, 1.7, 1.65, 1.3, 1.35, 1.5]
+
+# D3Q19: raw second moments xi_a xi_b with different rates per normal stress
+# (an anisotropic relaxation the built-in basis cannot express), the rest as
+# the built-in list
+RAW2_D3Q19 = ([[_t(1)], [_t(1, 1)], [_t(1, 0, 1)], [_t(1, 0, 0, 1)],
+               [_t(1, 2)], [_t(1, 0, 2)], [_t(1, 0, 0, 2)], [_t(1, 1, 1)], [_t(1, 0, 1, 1)], [_t(1, 1, 0, 1)]]
+              + [[_t(1, *e)] for e in [(1, 2, 0), (1, 0, 2), (2, 1, 0), (0, 1, 2), (2, 0, 1), (0, 2, 1),
+                                       (2, 2, 0), (2, 0, 2), (0, 2, 2)]])
+RATES_RAW2_D3Q19 = [0.0] * 4 + [1.1, 1.2, 1.3] + [1.95] * 3 + [1.5] * 6 + [1.2] * 3
+
+# D3Q27: the tensor Hermite-like family over exponents 0..2 per axis, in the
+# built-in monomial order
+_EXP27 = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (2, 0, 0), (0, 2, 0), (0, 0, 2), (1, 1, 0), (0, 1, 1),
+          (1, 0, 1), (1, 2, 0), (1, 0, 2), (2, 1, 0), (0, 1, 2), (2, 0, 1), (0, 2, 1), (1, 1, 1), (2, 2, 0),
+          (2, 0, 2), (0, 2, 2), (2, 1, 1), (1, 2, 1), (1, 1, 2), (2, 2, 1), (2, 1, 2), (1, 2, 2), (2, 2, 2)]
+HERMITE_D3Q27 = [_herm(*e) for e in _EXP27]
+RATES_HERMITE_D3Q27 = [0.0] * 4 + [1.1, 1.15, 1.2] + [1.95] * 3 + [1.5] * 7 + [1.3] * 3 + [1.2] * 7

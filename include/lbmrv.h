@@ -250,6 +250,25 @@ int lbmrv_moments(lbmrv_ctx *c, const void *f, void *rho, void *u, void *m0, voi
 int lbmrv_conservation(lbmrv_ctx *c, const void *f, double out[4], void *hip_stream);
 
 /*
+ * Distance of a state from a uniform reference state, for the growth rate of
+ * small perturbations (linear stability of the scheme about a uniform flow;
+ * the paper names stability as the question its schemes leave open).
+ *   f_ref  host array of q doubles: the reference populations (f itself, not
+ *          the stored deviations), e.g. one node of a uniform equilibrium
+ * lbmrv_deviation_norm: out[0] = sum over nodes and j of (f_j - f_ref_j)^2,
+ *   accumulated in FP64 in a fixed order (deterministic).  Blocking: returns
+ *   after the work queued on hip_stream is done.  Returns NONFINITE (out[0]
+ *   still written) when some population is NaN or infinite.
+ * lbmrv_deviation_scale: f_j <- f_ref_j + factor (f_j - f_ref_j) at every
+ *   node, in FP64 and then the storage's arithmetic type and rounding;
+ *   asynchronous on hip_stream.
+ * Errors: INVALID_ARG (null or misaligned f, null or non-finite f_ref,
+ * non-finite factor), HIP.
+ */
+int lbmrv_deviation_norm(lbmrv_ctx *c, const void *f, const double *f_ref, double *out, void *hip_stream);
+int lbmrv_deviation_scale(lbmrv_ctx *c, void *f, const double *f_ref, double factor, void *hip_stream);
+
+/*
  * Initial state (K5): f_out <- f^eq(rho, u) + noise_amp * noise, computed in
  * FP64 and stored in the context's storage type (minus w_j rho0 for the
  * deviation storages, rounded to nearest-even).

@@ -57,6 +57,8 @@ using MomFn = hipError_t (*)(const MomLaunch&);
 using ConsFn = hipError_t (*)(const void*, uint64_t, double*, hipStream_t);
 using InitFn = hipError_t (*)(const InitLaunch&);
 using ConvFn = hipError_t (*)(const void*, void*, double, uint64_t, int, hipStream_t);
+using DevNormFn = hipError_t (*)(const void*, uint64_t, const DevRef&, double*, hipStream_t);
+using DevScaleFn = hipError_t (*)(void*, uint64_t, const DevRef&, double, hipStream_t);
 
 struct Entry {
   StepFn step[3];
@@ -66,6 +68,8 @@ struct Entry {
   ConvFn conv[3];
   AdjFn adj[3];
   FinFn fin[3];
+  DevNormFn dnorm[3];
+  DevScaleFn dscale[3];
 };
 
 #define LBMRV_ENTRY(NAME)                                                                 \
@@ -76,7 +80,9 @@ struct Entry {
         {launch_init_##NAME##_f64, launch_init_##NAME##_f32, launch_init_##NAME##_f16},   \
         {launch_convert_##NAME##_f64, launch_convert_##NAME##_f32, launch_convert_##NAME##_f16}, \
         {launch_adjoint_##NAME##_f64, launch_adjoint_##NAME##_f32, launch_adjoint_##NAME##_f16}, \
-        {launch_aa_finish_##NAME##_f64, launch_aa_finish_##NAME##_f32, launch_aa_finish_##NAME##_f16} \
+        {launch_aa_finish_##NAME##_f64, launch_aa_finish_##NAME##_f32, launch_aa_finish_##NAME##_f16}, \
+        {launch_devnorm_##NAME##_f64, launch_devnorm_##NAME##_f32, launch_devnorm_##NAME##_f16}, \
+        {launch_devscale_##NAME##_f64, launch_devscale_##NAME##_f32, launch_devscale_##NAME##_f16} \
   }
 
 const Entry kEntries[4] = {LBMRV_ENTRY(d2q9_paper), LBMRV_ENTRY(d2q9_geier), LBMRV_ENTRY(d3q19),
@@ -780,6 +786,57 @@ int lbmrv_conservation(lbmrv_ctx* c, const void* f, double out[4], void* hip_str
   out[0] = h[0] + c->rho0 * (double)c->N;
   for (int a = 0; a < 3; ++a) out[1 + a] = a < c->d ? c->lambda * h[1 + a] : 0.0;
   return h[4] > 0 ? LBMRV_ERR_NONFINITE : LBMRV_OK;
+}
+
+// The reference populations in the stored representation; INVALID_ARG if
+// one is not finite.
+static int dev_ref(const lbmrv_ctx* c, const double* f_ref, DevRef& r) {
+  if (!f_ref) return LBMRV_ERR_INVALID_ARG;
+  double w[27] = {};
+  int32_t cd[81];
+  lbmrv_lattice_tables(c->lattice, cd, w);
+  for (int j = 0; j < 27; ++j) {
+    if (j < c->q && !std::isfinite(f_ref[j])) return LBMRV_ERR_INVALID_ARG;
+    r.r[j] = j < c->q ? f_ref[j] - w[j] * c->rho0 : 0.0;
+  }
+  return LBMRV_OK;
+}
+
+int lbmrv_deviation_norm(lbmrv_ctx* c, const void* f, const double* f_ref, double* out, void* hip_stream) {
+  if (!c || !out) return LBMRV_ERR_INVALID_ARG;
+  int rc;
+  DevRef r{};
+  if ((rc = check_ptr(f, elem_bytes(c->storage))) || (rc = dev_ref(c, f_ref, r))) return rc;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return LBMRV_ERR_HIP;
+  if (c->partial && c->partial_dev != dev) return LBMRV_ERR_INVALID_ARG;
+  if (!c->partial) {
+    if (hipMalloc(&c->partial, sizeof(double) * (kRedBlocks * 5 + 8)) != hipSuccess) {
+      c->partial = nullptr;
+      return LBMRV_ERR_HIP;
+    }
+    c->partial_dev = dev;
+  }
+  if (kEntries[c->entry].dnorm[c->sk](f, c->N, r, c->partial, st) != hipSuccess) return LBMRV_ERR_HIP;
+  double* res = c->partial + kRedBlocks * 5;
+  hipLaunchKernelGGL(k_conserve_final, dim3(1), dim3(kRedThreads), 0, st, c->partial, res);
+  if (hipGetLastError() != hipSuccess) return LBMRV_ERR_HIP;
+  double h[5];
+  if (hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess) return LBMRV_ERR_HIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return LBMRV_ERR_HIP;
+  out[0] = h[0];
+  return h[4] > 0 ? LBMRV_ERR_NONFINITE : LBMRV_OK;
+}
+
+int lbmrv_deviation_scale(lbmrv_ctx* c, void* f, const double* f_ref, double factor, void* hip_stream) {
+  if (!c || !std::isfinite(factor)) return LBMRV_ERR_INVALID_ARG;
+  int rc;
+  DevRef r{};
+  if ((rc = check_ptr(f, elem_bytes(c->storage))) || (rc = dev_ref(c, f_ref, r))) return rc;
+  return kEntries[c->entry].dscale[c->sk](f, c->N, r, factor, static_cast<hipStream_t>(hip_stream)) == hipSuccess
+             ? LBMRV_OK
+             : LBMRV_ERR_HIP;
 }
 
 int lbmrv_init_equilibrium(lbmrv_ctx* c, const double* rho, const double* u, const double* noise, double noise_amp,

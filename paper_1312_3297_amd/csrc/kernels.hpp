@@ -560,6 +560,66 @@ __global__ __launch_bounds__(kRedThreads) void k_conserve_partial(const void* fp
     for (int i = 0; i < 5; ++i) partial[(uint64_t)blockIdx.x * 5 + i] = red[i][0];
 }
 
+// Distance from a uniform reference state, for the growth rate of small
+// perturbations (linear stability).  ref[j] is the reference population in the
+// stored representation (f_ref_j - w_j rho0 for the deviation storages).
+struct DevRef {
+  double r[27];
+};
+
+// Squared distance sum_j (f_j - ref_j)^2 per node, block partial sums in FP64
+// in the 5-slot layout of k_conserve_partial (slot 0: the sum, slot 4: count
+// of non-finite values, slots 1-3: zero).
+template <class B, int ST>
+__global__ __launch_bounds__(kRedThreads) void k_dev_partial(const void* fp, uint64_t N, DevRef ref, double* partial) {
+  using S = typename Store<ST>::S;
+  constexpr int Q = B::Q;
+  const S* f = static_cast<const S*>(fp);
+  double acc = 0.0, bad = 0.0;
+  for (uint64_t n = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (uint64_t)gridDim.x * blockDim.x) {
+    sfor<Q>([&](auto jj) {
+      constexpr int J = jj;
+      const double v = double(f[(uint64_t)J * N + n]);
+      if (!__builtin_isfinite(v)) bad += 1.0;
+      const double d = v - ref.r[J];
+      acc = __builtin_fma(d, d, acc);
+    });
+  }
+  __shared__ double red[2][kRedThreads];
+  red[0][threadIdx.x] = acc;
+  red[1][threadIdx.x] = bad;
+  __syncthreads();
+  for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] += red[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 5) {
+    const double v = threadIdx.x == 0 ? red[0][0] : threadIdx.x == 4 ? red[1][0] : 0.0;
+    partial[(uint64_t)blockIdx.x * 5 + threadIdx.x] = v;
+  }
+}
+
+// f_j <- ref_j + factor (f_j - ref_j) at every node (FP64, then the storage's
+// arithmetic type and rounding).
+template <class B, int ST>
+__global__ __launch_bounds__(256) void k_dev_scale(void* fp, uint64_t N, DevRef ref, double factor) {
+  using S = typename Store<ST>::S;
+  using T = typename Store<ST>::T;
+  constexpr int Q = B::Q;
+  const uint64_t n = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  S* f = static_cast<S*>(fp);
+  sfor<Q>([&](auto jj) {
+    constexpr int J = jj;
+    const uint64_t i = (uint64_t)J * N + n;
+    const double v = ref.r[J] + factor * (double(f[i]) - ref.r[J]);
+    f[i] = S(T(v));
+  });
+}
+
 // Sums kRedBlocks partials in a fixed order (one block), deterministic.
 __global__ __launch_bounds__(kRedThreads) void k_conserve_final(const double* partial, double* out);
 

@@ -137,6 +137,18 @@ hipError_t launch_conserve_partial(const void* f, uint64_t N, double* partial, h
   return hipGetLastError();
 }
 
+template <class B, int ST>
+hipError_t launch_devnorm_t(const void* f, uint64_t N, const DevRef& ref, double* partial, hipStream_t st) {
+  hipLaunchKernelGGL((k_dev_partial<B, ST>), dim3(kRedBlocks), dim3(kRedThreads), 0, st, f, N, ref, partial);
+  return hipGetLastError();
+}
+
+template <class B, int ST>
+hipError_t launch_devscale_t(void* f, uint64_t N, const DevRef& ref, double factor, hipStream_t st) {
+  hipLaunchKernelGGL((k_dev_scale<B, ST>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, f, N, ref, factor);
+  return hipGetLastError();
+}
+
 struct InitLaunch {
   const double* rho;
   const double* u;
@@ -231,7 +243,11 @@ hipError_t launch_adjoint_s(const AdjLaunch& L) {
   hipError_t launch_aa_finish_##NAME##_##SKN(void* f, uint32_t nx, uint32_t ny, uint32_t nz, uint64_t N, \
                                              hipStream_t st);                                \
   hipError_t launch_convert_##NAME##_##SKN(const void* in, void* out, double rho0, uint64_t N, \
-                                           int to_storage, hipStream_t st);
+                                           int to_storage, hipStream_t st);                  \
+  hipError_t launch_devnorm_##NAME##_##SKN(const void* f, uint64_t N, const DevRef& ref,    \
+                                           double* partial, hipStream_t st);                \
+  hipError_t launch_devscale_##NAME##_##SKN(void* f, uint64_t N, const DevRef& ref, double factor, \
+                                            hipStream_t st);
 
 #define LBMRV_DEFINE_LAUNCHERS(NAME, BASIS, SKN, ST)                                        \
   hipError_t launch_step_##NAME##_##SKN(const StepLaunch& L) { return launch_step_s<BASIS, ST>(L); } \
@@ -251,6 +267,14 @@ hipError_t launch_adjoint_s(const AdjLaunch& L) {
   hipError_t launch_convert_##NAME##_##SKN(const void* in, void* out, double rho0, uint64_t N, \
                                            int to_storage, hipStream_t st) {               \
     return launch_convert_t<BASIS, ST>(in, out, rho0, N, to_storage, st);                   \
+  }                                                                                         \
+  hipError_t launch_devnorm_##NAME##_##SKN(const void* f, uint64_t N, const DevRef& ref,    \
+                                           double* partial, hipStream_t st) {               \
+    return launch_devnorm_t<BASIS, ST>(f, N, ref, partial, st);                             \
+  }                                                                                         \
+  hipError_t launch_devscale_##NAME##_##SKN(void* f, uint64_t N, const DevRef& ref, double factor, \
+                                            hipStream_t st) {                               \
+    return launch_devscale_t<BASIS, ST>(f, N, ref, factor, st);                             \
   }
 
 #define LBMRV_DECLARE_ALL(NAME) \

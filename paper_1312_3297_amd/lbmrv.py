@@ -55,6 +55,9 @@ _SIGS = {
     "lbmrv_adjoint_workspace_bytes": (ctypes.c_size_t, [_c_void_p, _c_int64, _c_int64]),
     "lbmrv_adjoint": (_c_int, [_c_void_p, _c_void_p, _c_int, _c_double, _c_void_p, _c_int64, _c_int64, _c_void_p,
                                _c_void_p, ctypes.c_size_t, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
+    "lbmrv_deviation_norm": (_c_int, [_c_void_p, _c_void_p, ctypes.POINTER(_c_double), ctypes.POINTER(_c_double),
+                                      _c_void_p]),
+    "lbmrv_deviation_scale": (_c_int, [_c_void_p, _c_void_p, ctypes.POINTER(_c_double), _c_double, _c_void_p]),
     "lbmrv_destroy": (None, [_c_void_p]),
     "lbmrv_strerror": (ctypes.c_char_p, [_c_int]),
 }
@@ -270,6 +273,20 @@ class Lbmrv:
                                        _ptr(cot_fN), _ptr(workspace), nbytes, _ptr(fN), _ptr(grad_f0),
                                        _ptr(grad_s), _ptr(grad_ut), _stream(stream)), "lbmrv_adjoint")
         return fN, grad_f0, grad_s, grad_ut
+
+    def deviation_norm2(self, f, f_ref, stream=None):
+        """sum over nodes and j of (f_j - f_ref_j)^2 (FP64) and whether f is finite."""
+        ref = (_c_double * self.q)(*[float(x) for x in f_ref])
+        out = (_c_double * 1)()
+        rc = library().lbmrv_deviation_norm(self._h, _ptr(f), ref, out, _stream(stream))
+        if rc not in (OK, ERR_NONFINITE):
+            _check(rc, "lbmrv_deviation_norm")
+        return out[0], rc == OK
+
+    def deviation_scale(self, f, f_ref, factor, stream=None):
+        ref = (_c_double * self.q)(*[float(x) for x in f_ref])
+        _check(library().lbmrv_deviation_scale(self._h, _ptr(f), ref, float(factor), _stream(stream)),
+               "lbmrv_deviation_scale")
 
     def import_f64(self, f, out=None, stream=None):
         out = self.empty(f.device) if out is None else out

@@ -143,3 +143,19 @@ def test_walls_and_streaming_validation_before_any_hip_call():
     assert lib.lbmrv_step(ctx._h, a, a, 0, 1.0, None, 1, st) == lbmrv.ERR_INVALID_ARG   # in place needs AA
     assert lib.lbmrv_adjoint(ctx._h, a, 0, 1.0, None, 4, 2, b, ctypes.c_void_p(1 << 20), 1 << 30, None,
                              ctypes.c_void_p(12288), ctypes.c_void_p(16384), None, st) == lbmrv.ERR_UNSUPPORTED
+
+
+def test_deviation_calls_validate_before_any_hip_call():
+    ctx = lbmrv.Lbmrv("d2q9", GOOD9, (8, 8), storage="f64")
+    lib = lbmrv.library()
+    st = ctypes.c_void_p(0)
+    ref = (ctypes.c_double * 9)(*([0.1] * 9))
+    bad = (ctypes.c_double * 9)(*([0.1] * 8 + [float("nan")]))
+    out = (ctypes.c_double * 1)()
+    a = ctypes.c_void_p(4096)
+    assert lib.lbmrv_deviation_norm(ctx._h, a, None, out, st) == lbmrv.ERR_INVALID_ARG
+    assert lib.lbmrv_deviation_norm(ctx._h, a, bad, out, st) == lbmrv.ERR_INVALID_ARG
+    assert lib.lbmrv_deviation_norm(ctx._h, a, ref, None, st) == lbmrv.ERR_INVALID_ARG
+    assert lib.lbmrv_deviation_norm(ctx._h, ctypes.c_void_p(4100), ref, out, st) == lbmrv.ERR_ALIGNMENT
+    assert lib.lbmrv_deviation_scale(ctx._h, a, ref, float("inf"), st) == lbmrv.ERR_INVALID_ARG
+    assert lib.lbmrv_deviation_scale(ctx._h, None, ref, 2.0, st) == lbmrv.ERR_INVALID_ARG

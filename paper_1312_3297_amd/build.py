@@ -49,13 +49,14 @@ def build(jobs=None, verbose=True):
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (r.stdout, r.stderr))
     os.replace(tmp, LIB)
-    # the bandwidth/counter calibration program (not part of the library)
-    cal = os.path.join(PKG, "calibrate", "copy_bw.hip")
-    exe = os.path.join(PKG, "calibrate", "copy_bw")
-    r = subprocess.run([HIPCC] + FLAGS + [cal, "-o", exe + ".tmp"], capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError("calibration build failed:\n%s\n%s" % (r.stdout, r.stderr))
-    os.replace(exe + ".tmp", exe)
+    # the bandwidth/counter calibration programs (not part of the library)
+    for name in ("copy_bw", "stream_q"):
+        cal = os.path.join(PKG, "calibrate", name + ".hip")
+        exe = os.path.join(PKG, "calibrate", name)
+        r = subprocess.run([HIPCC] + FLAGS + [cal, "-o", exe + ".tmp"], capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("calibration build failed:\n%s\n%s" % (r.stdout, r.stderr))
+        os.replace(exe + ".tmp", exe)
     if verbose:
         print("built", LIB, file=sys.stderr)
     return LIB

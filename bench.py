@@ -178,7 +178,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(domain decomposition across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 

@@ -71,7 +71,7 @@ extern "C" {
 
 #define LBMRV_OK 0
 #define LBMRV_ERR_INVALID_ARG (-1)   /* a pointer, size, enum or rate is invalid    */
-#define LBMRV_ERR_UNSUPPORTED (-2)   /* valid request that this build cannot serve  */
+#define LBMRV_ERR_UNSUPPORTED (-2)   /* valid request the library does not serve    */
 #define LBMRV_ERR_HIP (-4)           /* a HIP runtime call failed                   */
 #define LBMRV_ERR_NONFINITE (-5)     /* lbmrv_conservation found a NaN or infinity  */
 #define LBMRV_ERR_ALIGNMENT (-6)     /* a pointer is not aligned to its element     */

@@ -70,8 +70,7 @@ def library():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
-            raise ImportError("liblbmrv.so not built: run __graft_entry__.build() "
-                              "(or python paper_1312_3297_amd/build.py) first")
+            raise ImportError("liblbmrv.so not built: run python paper_1312_3297_amd/build.py first")
         lib = ctypes.CDLL(_LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(lib, name)

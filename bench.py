@@ -26,8 +26,20 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the fused collide-stream kernel (GB), from rocprofv3
 # FETCH_SIZE and WRITE_SIZE counters scaled by what the same counters read for
 # a plain copy of known size (FETCH x 2.0, WRITE x 1.0); see profiles/.  Only
-# valid for the kernel version the counters were taken on.
-TRAFFIC_GB = {("d3q19_tgv256_f32_fluid", "pull"): 2.5513}
+# valid for the kernel version the counters were taken on, in the default
+# (automatic) block order; the in-place form averages its two kernels.
+TRAFFIC_GB = {
+    ("d3q19_tgv256_f32_fluid", "pull"): 2.5514,
+    ("d3q19_tgv256_f16dev_fluid", "pull"): 1.2752,
+    ("d3q27_tgv192_f32_field", "pull"): 1.614,
+    ("d2q9_shear4096_f32_fluid", "pull"): 1.2584,
+    ("d2q9_shear2048_f32_fluid", "pull"): 0.3021,
+    ("d3q19_tgv256_f32_fluid", "aa"): 2.5506,
+    ("d2q9_shear2048_f32_fluid", "aa"): 0.3021,
+    ("d3q19_tgv256_f32_fluid", "push"): 2.5601,
+    ("d3q19_couette256_f32_fluid_walls", "pull"): 2.5539,
+    ("d3q19_tgv256_f32_fluid_rawbasis", "pull"): 2.5536,
+}
 
 WORKLOADS = {
     # name: (lattice, dims, storage, mode, alpha, builder)
@@ -173,6 +185,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="d3q19_tgv256_f32_fluid", choices=sorted(WORKLOADS))
     ap.add_argument("--streaming", default="pull", choices=["pull", "push", "aa"])
+    ap.add_argument("--block-order", default="auto", choices=["auto", "natural", "xcd"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
@@ -194,6 +207,7 @@ def main():
     else:
         ctx = Lbmrv(lattice, rates_for(lattice), dims, storage)
     ctx.set_streaming(args.streaming)
+    ctx.set_block_order(args.block_order)
     if name in WALLS:
         mask, uwall = WALLS[name]
         wu = [[0.0, 0.0, 0.0] for _ in range(6)]
@@ -249,10 +263,11 @@ def main():
         "dtype": {"f64": "f64", "f32": "f32", "f32dev": "f32", "f16dev": "f16-storage/f32"}[storage],
         "data": "synthetic",
         "config": {"workload": name, "lattice": lattice, "grid": list(dims), "storage": storage,
-                   "relative_velocity": mode, "streaming": args.streaming, "nodes": N},
+                   "relative_velocity": mode, "streaming": args.streaming, "block_order": args.block_order,
+                   "nodes": N},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": TRAFFIC_GB.get((name, args.streaming))},
+                     "traffic": TRAFFIC_GB.get((name, args.streaming)) if args.block_order == "auto" else None},
         "state_finite": bool(finite),
         "wall_s": round(wall, 4),
     }

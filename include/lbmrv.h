@@ -82,6 +82,7 @@ enum lbmrv_storage { LBMRV_F64 = 0, LBMRV_F32 = 1, LBMRV_F32DEV = 2, LBMRV_F16DE
 enum lbmrv_utmode { LBMRV_UT_ZERO = 0, LBMRV_UT_FLUID = 1, LBMRV_UT_FIELD = 2 };
 enum lbmrv_streaming { LBMRV_STREAM_PULL = 0, LBMRV_STREAM_PUSH = 1, LBMRV_STREAM_AA = 2 };
 enum lbmrv_equilibrium { LBMRV_EQ_POLYNOMIAL = 0, LBMRV_EQ_MAXWELLIAN = 1 };
+enum lbmrv_block_order { LBMRV_ORDER_AUTO = 0, LBMRV_ORDER_NATURAL = 1, LBMRV_ORDER_XCD = 2 };
 
 typedef struct lbmrv_ctx lbmrv_ctx;
 
@@ -188,6 +189,21 @@ int lbmrv_set_equilibrium(lbmrv_ctx *c, int kind);
  * UNSUPPORTED for the others, lbmrv_adjoint for any wall).  No HIP call.
  */
 int lbmrv_set_walls(lbmrv_ctx *c, uint32_t wall_mask, const double *wall_u, double rho_w);
+
+/*
+ * Order in which the step kernels' workgroups take their tiles.  The GPU
+ * deals workgroups to its eight XCDs (each with its own L2) round-robin:
+ *   LBMRV_ORDER_NATURAL: tiles in grid order, so the eight XCDs work on
+ *     neighbouring addresses at any moment;
+ *   LBMRV_ORDER_XCD: each XCD takes one contiguous range of tiles, so tiles
+ *     that are neighbours along x (sharing the cache lines at their common
+ *     edge) meet in one L2;
+ *   LBMRV_ORDER_AUTO (default): XCD while the population array (q N
+ *     elements) fits in 256 MiB, NATURAL beyond (the faster choice measured
+ *     on both sides of that size).
+ * Results are identical bit for bit in every order.  No HIP call.
+ */
+int lbmrv_set_block_order(lbmrv_ctx *c, int order);
 
 /*
  * Replay of repeated step launches through HIP graphs (default off): the first

@@ -111,6 +111,7 @@ struct lbmrv_ctx {
   double wall_u[6][3] = {};   // wall velocities (physical units)
   double rho_w = 1.0;
   int equilibrium = LBMRV_EQ_POLYNOMIAL;
+  int block_order = LBMRV_ORDER_AUTO;
   // replay of repeated launches through HIP graphs (see run_alternating)
   struct GraphEntry {
     int kind_a, kind_b;
@@ -183,6 +184,10 @@ StepLaunch base_launch(const lbmrv_ctx* c, hipStream_t st) {
   for (int f = 0; f < 6; ++f)
     for (int ax = 0; ax < 3; ++ax) L.wall_coef[f][ax] = 6.0 * c->rho_w * c->wall_u[f][ax] / c->lambda;
   L.relax = c->custom ? c->dtab : nullptr;
+  // contiguous tile ranges per XCD while the population array (q N elements)
+  // fits in the 256 MiB last-level cache (measured faster there, slower beyond)
+  const bool small = (uint64_t)elem_bytes(c->storage) * c->q * c->N <= (256ull << 20);
+  L.xcd_remap = c->block_order == LBMRV_ORDER_XCD || (c->block_order == LBMRV_ORDER_AUTO && small) ? 1u : 0u;
   L.stream = st;
   L.block = c->block;
   return L;
@@ -605,6 +610,14 @@ int lbmrv_set_streaming(lbmrv_ctx* c, int kind) {
 int lbmrv_set_equilibrium(lbmrv_ctx* c, int kind) {
   if (!c || (kind != LBMRV_EQ_POLYNOMIAL && kind != LBMRV_EQ_MAXWELLIAN)) return LBMRV_ERR_INVALID_ARG;
   c->equilibrium = kind;
+  ++c->version;
+  return LBMRV_OK;
+}
+
+int lbmrv_set_block_order(lbmrv_ctx* c, int order) {
+  if (!c || (order != LBMRV_ORDER_AUTO && order != LBMRV_ORDER_NATURAL && order != LBMRV_ORDER_XCD))
+    return LBMRV_ERR_INVALID_ARG;
+  c->block_order = order;
   ++c->version;
   return LBMRV_OK;
 }

@@ -28,6 +28,7 @@ struct StepLaunch {
   double wall_coef[6][3];
   uint32_t eq_maxwell;
   const void* relax;  // run-time basis: R^{-1} S R block in the arithmetic type, or null
+  uint32_t xcd_remap; // block order (see block_tile)
   hipStream_t stream;
   int block;   // threads per block along x
 };
@@ -62,6 +63,7 @@ hipError_t launch_step_t(const StepLaunch& L) {
   a.wall_mask = L.wall_mask;
   a.eq_maxwell = L.eq_maxwell;
   a.relax = static_cast<const T*>(L.relax);
+  a.xcd_remap = L.xcd_remap;
   for (int f = 0; f < 6; ++f)
     for (int ax = 0; ax < 3; ++ax) a.wall_coef[f][ax] = T(L.wall_coef[f][ax]);
   // block: whole wavefronts along x (at most 256 threads), and for the gather

@@ -18,6 +18,7 @@ STORAGES = {"f64": 0, "f32": 1, "f32dev": 2, "f16dev": 3}
 MODES = {"zero": 0, "fluid": 1, "field": 2}
 STREAMING = {"pull": 0, "push": 1, "aa": 2}
 EQUILIBRIA = {"polynomial": 0, "maxwellian": 1}
+BLOCK_ORDERS = {"auto": 0, "natural": 1, "xcd": 2}
 QD = {"d2q9": (9, 2), "d3q19": (19, 3), "d3q27": (27, 3)}
 
 _c_void_p = ctypes.c_void_p
@@ -41,6 +42,7 @@ _SIGS = {
     "lbmrv_set_walls": (_c_int, [_c_void_p, ctypes.c_uint32, ctypes.POINTER(_c_double), _c_double]),
     "lbmrv_set_equilibrium": (_c_int, [_c_void_p, _c_int]),
     "lbmrv_set_graphs": (_c_int, [_c_void_p, _c_int]),
+    "lbmrv_set_block_order": (_c_int, [_c_void_p, _c_int]),
     "lbmrv_info": (_c_int, [_c_void_p] + [ctypes.POINTER(_c_int64)] * 4),
     "lbmrv_step": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_int, _c_double, _c_void_p, _c_int64, _c_void_p]),
     "lbmrv_collide": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_int, _c_double, _c_void_p, _c_void_p]),
@@ -198,6 +200,9 @@ class Lbmrv:
 
     def set_streaming(self, kind):
         _check(library().lbmrv_set_streaming(self._h, STREAMING[kind]), "lbmrv_set_streaming")
+
+    def set_block_order(self, order):
+        _check(library().lbmrv_set_block_order(self._h, BLOCK_ORDERS[order]), "lbmrv_set_block_order")
 
     def set_graphs(self, enable):
         _check(library().lbmrv_set_graphs(self._h, 1 if enable else 0), "lbmrv_set_graphs")

@@ -159,3 +159,12 @@ def test_deviation_calls_validate_before_any_hip_call():
     assert lib.lbmrv_deviation_norm(ctx._h, ctypes.c_void_p(4100), ref, out, st) == lbmrv.ERR_ALIGNMENT
     assert lib.lbmrv_deviation_scale(ctx._h, a, ref, float("inf"), st) == lbmrv.ERR_INVALID_ARG
     assert lib.lbmrv_deviation_scale(ctx._h, None, ref, 2.0, st) == lbmrv.ERR_INVALID_ARG
+
+
+def test_block_order_validation():
+    ctx = lbmrv.Lbmrv("d2q9", GOOD9, (8, 8), storage="f32")
+    lib = lbmrv.library()
+    for order in (0, 1, 2):
+        assert lib.lbmrv_set_block_order(ctx._h, order) == lbmrv.OK
+    assert lib.lbmrv_set_block_order(ctx._h, 3) == lbmrv.ERR_INVALID_ARG
+    assert lib.lbmrv_set_block_order(None, 0) == lbmrv.ERR_INVALID_ARG

@@ -36,6 +36,7 @@ struct AdjArgs {
   T s[27];
   const T* rnn;     // run-time basis only: non-conserved block of R (P = R W), (Q-D-1)^2 row-major
   const T* rnninv;  // and its inverse
+  uint32_t xcd_remap;  // block order, as for the step kernels (block_tile)
 };
 
 template <class B, int ST, int MODE, int RLX>
@@ -47,10 +48,11 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
   constexpr int Q = B::Q;
   constexpr int D = L::D;
 
-  const uint32_t xr = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint3 tile = block_tile(a.xcd_remap);
+  const uint32_t xr = tile.x * blockDim.x + threadIdx.x;
   const bool active = xr < a.nx;
   const uint32_t x = active ? xr : a.nx - 1;  // inactive lanes recompute a valid node, store nothing
-  const uint32_t y = blockIdx.y, z = blockIdx.z;
+  const uint32_t y = tile.y, z = tile.z;
   const uint32_t nx = a.nx, ny = a.ny, nz = a.nz;
   const uint32_t xp = x == nx - 1 ? 0 : x + 1, xm = x == 0 ? nx - 1 : x - 1;
   const uint32_t yp = y == ny - 1 ? 0 : y + 1, ym = y == 0 ? ny - 1 : y - 1;
@@ -301,7 +303,8 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
   // dJ/ds_k: block sum of z3_k r_k in FP64, added to this block's row
   __shared__ double red[4][Q];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint32_t bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  // one row per tile (not per workgroup), so the sums do not depend on the block order
+  const uint32_t bid = tile.x + gridDim.x * (tile.y + gridDim.y * tile.z);
   sfor<Q>([&](auto kk) {
     constexpr int K = kk;
     if constexpr (K > D) {

@@ -168,6 +168,13 @@ int check_mode(const lbmrv_ctx* c, int ut_mode, double ut_alpha, const float* ut
   return LBMRV_OK;
 }
 
+// Contiguous tile ranges per XCD while the population array (q N elements)
+// fits in the 256 MiB last-level cache (measured faster there, slower beyond).
+uint32_t xcd_order(const lbmrv_ctx* c) {
+  const bool small = (uint64_t)elem_bytes(c->storage) * c->q * c->N <= (256ull << 20);
+  return c->block_order == LBMRV_ORDER_XCD || (c->block_order == LBMRV_ORDER_AUTO && small) ? 1u : 0u;
+}
+
 StepLaunch base_launch(const lbmrv_ctx* c, hipStream_t st) {
   StepLaunch L{};
   L.sk = c->sk;
@@ -184,10 +191,7 @@ StepLaunch base_launch(const lbmrv_ctx* c, hipStream_t st) {
   for (int f = 0; f < 6; ++f)
     for (int ax = 0; ax < 3; ++ax) L.wall_coef[f][ax] = 6.0 * c->rho_w * c->wall_u[f][ax] / c->lambda;
   L.relax = c->custom ? c->dtab : nullptr;
-  // contiguous tile ranges per XCD while the population array (q N elements)
-  // fits in the 256 MiB last-level cache (measured faster there, slower beyond)
-  const bool small = (uint64_t)elem_bytes(c->storage) * c->q * c->N <= (256ull << 20);
-  L.xcd_remap = c->block_order == LBMRV_ORDER_XCD || (c->block_order == LBMRV_ORDER_AUTO && small) ? 1u : 0u;
+  L.xcd_remap = xcd_order(c);
   L.stream = st;
   L.block = c->block;
   return L;
@@ -1006,6 +1010,7 @@ int lbmrv_adjoint(lbmrv_ctx* c, const void* f0, int ut_mode, double ut_alpha, co
   for (int k = 0; k < 27; ++k) A.s[k] = k < c->q ? c->s[k] : 0.0;
   A.rnn = tab_ptr(c, 2);
   A.rnninv = tab_ptr(c, 3);
+  A.xcd_remap = xcd_order(c);
   A.stream = st;
   A.block = c->block;
   // reverse sweep, one segment of K steps at a time; the last segment's states

@@ -389,7 +389,9 @@ __global__ __launch_bounds__(step_max_threads<ST>()) void k_step(StepArgs<typena
   sfor<Q>([&](auto jj) {
     constexpr int J = jj;
     if constexpr (KIND == K_PUSH || KIND == K_AA_ODD) {
-      fout[(uint64_t)J * N + nbr(jj, std::integral_constant<int, 1>{})] = S(h[J]);
+      S* dst = &fout[(uint64_t)J * N + nbr(jj, std::integral_constant<int, 1>{})];
+      if constexpr (L::c[J].x == 0) __builtin_nontemporal_store(S(h[J]), dst);  // aligned with the wavefront
+      else *dst = S(h[J]);
     } else {
       constexpr int slot = KIND == K_AA_EVEN ? opposite<L>(J) : J;
       __builtin_nontemporal_store(S(h[J]), &fout[(uint64_t)slot * N + own]);

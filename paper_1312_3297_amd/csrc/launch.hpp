@@ -190,6 +190,7 @@ struct AdjLaunch {
   double s[27];
   const void* rnn;     // run-time basis: non-conserved block of R and its inverse, or null
   const void* rnninv;
+  uint32_t xcd_remap;
   hipStream_t stream;
   int block;
 };
@@ -214,6 +215,7 @@ hipError_t launch_adjoint_t(const AdjLaunch& L) {
   for (int k = 0; k < 27; ++k) a.s[k] = T(L.s[k]);
   a.rnn = static_cast<const T*>(L.rnn);
   a.rnninv = static_cast<const T*>(L.rnninv);
+  a.xcd_remap = L.xcd_remap;
   const int bx = L.block;
   dim3 grid((L.nx + bx - 1) / bx, L.ny, L.nz);
   hipLaunchKernelGGL((k_adjoint<B, ST, MODE, RLX>), grid, dim3(bx), 0, L.stream, a);

@@ -112,22 +112,34 @@ def cpu_baseline(name, budget_s=15.0):
     f = scheme.equilibrium(lat, rho, u)
     smode = {"zero": scheme.ZERO, "fluid": scheme.FLUID, "field": scheme.FIELD}[mode]
     field = 0.5 * u if mode == "field" else None
-    threads = min(16, os.cpu_count() or 1)
-    t0 = time.perf_counter()
-    steps = 0
-    chunk = 1
-    while True:
-        f = fast.run(lat, f, s, chunk, 1.0, smode, 1.0, field, threads=threads)
-        steps += chunk
-        el = time.perf_counter() - t0
-        if el >= budget_s:
-            break
-        chunk = max(1, min(64, int(steps * (budget_s - el) / el / 4)))
     nodes = int(np.prod(sub))
+
+    def timed(fn, f, budget):
+        """Steps fn(f, n) in growing chunks for about `budget` seconds; (steps, seconds)."""
+        t0 = time.perf_counter()
+        steps, chunk = 0, 1
+        while True:
+            f = fn(f, chunk)
+            steps += chunk
+            el = time.perf_counter() - t0
+            if el >= budget:
+                return steps, el
+            chunk = max(1, min(64, int(steps * (budget - el) / el / 4)))
+
+    threads = min(16, os.cpu_count() or 1)
+    steps, el = timed(lambda g, n: fast.run(lat, g, s, n, 1.0, smode, 1.0, field, threads=threads), f, budget_s)
+    # the same on one core, and Oracle A (NumPy) on the 64^2 D2Q9 shear wave
+    steps1, el1 = timed(lambda g, n: fast.run(lat, g, s, n, 1.0, smode, 1.0, field, threads=1), f, budget_s / 3)
+    lat_a = lattices.make("d2q9_paper")
+    rho_a, u_a = W.shear_wave(64, 0.01)
+    steps_a, el_a = timed(lambda g, n: scheme.run(lat_a, g, W.RATES_D2Q9_GROUPED, n, mode=scheme.FLUID),
+                          scheme.equilibrium(lat_a, rho_a, u_a), budget_s / 3)
     return {"value": round(nodes * steps / el / 1e6, 4), "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": "Oracle B (C, FP64, OpenMP, per-node Gaussian elimination) on a %s periodic sub-block of "
                       "the same initial state, %d steps in %.1f s" % ("x".join(str(x) for x in reversed(sub)),
-                                                                       steps, el)}
+                                                                       steps, el),
+            "one_core_value": round(nodes * steps1 / el1 / 1e6, 4),
+            "oracle_a_d2q9_64_mlups": round(64 * 64 * steps_a / el_a / 1e6, 4)}
 
 
 def adjoint_cost(torch, L=512, nsteps=2000, K=100, reps=2):

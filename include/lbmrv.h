@@ -55,6 +55,12 @@
  * its parameters, (after the first lbmrv_conservation call) a small device
  * buffer for partial sums and, for a run-time basis, a small device table.
  *
+ * Concurrency.  A context is not thread-safe: calls on one context must not
+ * run concurrently from several host threads.  lbmrv_conservation and
+ * lbmrv_deviation_norm share the context's partial-sum buffer; they are
+ * blocking, so successive calls never overlap on the device.  Different
+ * contexts are independent.
+ *
  * Errors.  Every int-returning call returns LBMRV_OK (0) or a negative code.
  * Arguments are validated on the host before any HIP call, so an invalid call
  * has no device-side effect.  lbmrv_strerror gives a message.

@@ -16,4 +16,9 @@ mrt        Oracle C: the d'Humieres MRT step of section 1.1, written separately
 geier      Oracle D: the cascaded g-vector form of Appendix B
 adjoint    Oracle E: discrete adjoint / tangent of Oracle A's step (FP64)
 fast       Oracle B: the same definition in plain C with OpenMP (liboracle_fast)
+stability  Oracle F: linear (von Neumann) stability about a uniform flow, from
+           the Jacobian of Oracle E's step and the transport phases
+
+lattices.with_basis builds a lattice with a run-time polynomial basis given as
+term lists (used to check the library's run-time bases).
 """

@@ -68,8 +68,12 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
     const uint32_t xx = cx == 0 ? x : (cx > 0 ? xp : xm);
     const uint32_t yy = cy == 0 ? y : (cy > 0 ? yp : ym);
     const uint32_t zz = cz == 0 ? z : (cz > 0 ? zp : zm);
-    h[J] = T(f[(uint64_t)J * N + own]);
-    g[J] = a.lam_in[(uint64_t)J * N + (zz * ny + yy) * nx + xx];
+    // accesses aligned with the wavefront stream past the caches; the +-1
+    // shifted gathers along x share lines with the neighbouring wavefront
+    h[J] = T(__builtin_nontemporal_load(&f[(uint64_t)J * N + own]));
+    const T* src = &a.lam_in[(uint64_t)J * N + (zz * ny + yy) * nx + xx];
+    if constexpr (cx == 0) g[J] = __builtin_nontemporal_load(src);
+    else g[J] = *src;
   });
 
   // ---- forward quantities at this node
@@ -296,7 +300,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
         constexpr int cj = al == 0 ? L::c[J].x : al == 1 ? L::c[J].y : L::c[J].z;
         lam = fmac(Bv[al], T(cj) - u[al], lam);
       });
-      lo[(uint64_t)J * N + own] = lam;
+      __builtin_nontemporal_store(lam, &lo[(uint64_t)J * N + own]);
     });
   }
 

@@ -167,3 +167,32 @@ def test_custom_basis_adjoint_matches_autodiff_oracle(case, mode):
     assert rel(gs, gs_ref) <= 1e-10
     if mode == "field":
         assert rel(gu.cpu().numpy(), gu_ref) <= 1e-10
+
+
+@pytest.mark.parametrize("case", ["d2q9_hermite", "d3q27_hermite"])
+def test_custom_basis_with_maxwellian_equilibria_and_walls_fp64(case):
+    """A run-time basis combined with the Maxwellian equilibria and with
+    half-way bounce-back walls (one moving) against the oracle with the same
+    polynomials, equilibrium and walls."""
+    lattice, polys, s, shape = CASES[case]
+    lat = lattices.with_basis(lattice, polys)
+    f0 = far_state(lat, shape, seed=39, amp=0.02, umax=0.06)
+    mask = (1 << 2) | (1 << 3)
+    uw = [[0.0, 0.0, 0.0] for _ in range(6)]
+    uw[3] = [0.02, 0.0, 0.0]
+    n = 4
+    ctx = Lbmrv(lattice, s, tuple(reversed(shape)), "f64", basis=polys)
+    ctx.set_equilibrium("maxwellian")
+    ref = A.run(lat, f0, s, n, mode=A.FLUID, eq="maxwellian")
+    a = torch.from_numpy(f0).cuda()
+    b = torch.empty_like(a)
+    ctx.step(a, b, "fluid", 1.0, None, n)
+    torch.cuda.synchronize()
+    assert rel(b.cpu().numpy(), ref) <= 1e-12
+    ctx.set_equilibrium("polynomial")
+    ctx.set_walls(mask, uw, 1.0)
+    ref = A.run(lat, f0, s, n, mode=A.FLUID, walls=(mask, uw, 1.0))
+    a = torch.from_numpy(f0).cuda()
+    ctx.step(a, b, "fluid", 1.0, None, n)
+    torch.cuda.synchronize()
+    assert rel(b.cpu().numpy(), ref) <= 1e-12

@@ -191,8 +191,13 @@ int lbmrv_set_equilibrium(lbmrv_ctx *c, int kind);
  * post-collision opposite population plus 2 w_j rho_w (v_j . u_w) / cs2 for a
  * wall moving at u_w (wall_u [6][3], physical units, face index 2a + side,
  * NULL = all at rest); at an edge the first crossed wall face in axis order
- * gives u_w.  Only the pull form supports walls (lbmrv_step returns
- * UNSUPPORTED for the others, lbmrv_adjoint for any wall).  No HIP call.
+ * gives u_w.  The pull form supports any wall_mask.  The in-place form
+ * supports walls placed on both faces of an axis (with a wall on one face
+ * only, lbmrv_step returns UNSUPPORTED): there a population bounced at step n
+ * is kept in the node's own opposite slot; its results equal the pull form's
+ * bit for bit in FP64 and FP32 storage (FP16: the moving-wall term is added
+ * before instead of after one storage rounding).  The push form returns
+ * UNSUPPORTED, and so does lbmrv_adjoint for any wall.  No HIP call.
  */
 int lbmrv_set_walls(lbmrv_ctx *c, uint32_t wall_mask, const double *wall_u, double rho_w);
 

@@ -52,7 +52,7 @@ namespace {
 
 using StepFn = hipError_t (*)(const StepLaunch&);
 using AdjFn = hipError_t (*)(const AdjLaunch&);
-using FinFn = hipError_t (*)(void*, uint32_t, uint32_t, uint32_t, uint64_t, hipStream_t);
+using FinFn = hipError_t (*)(void*, uint32_t, uint32_t, uint32_t, uint64_t, const FinArgs&, hipStream_t);
 using MomFn = hipError_t (*)(const MomLaunch&);
 using ConsFn = hipError_t (*)(const void*, uint64_t, double*, hipStream_t);
 using InitFn = hipError_t (*)(const InitLaunch&);
@@ -669,7 +669,12 @@ int lbmrv_step(lbmrv_ctx* c, void* f_in, void* f_out, int ut_mode, double ut_alp
   if (nsteps < 0) return LBMRV_ERR_INVALID_ARG;
   if (f_in == f_out && c->streaming != LBMRV_STREAM_AA) return LBMRV_ERR_INVALID_ARG;
   if ((rc = check_mode(c, ut_mode, ut_alpha, ut_field))) return rc;
-  if (c->wall_mask && c->streaming != LBMRV_STREAM_PULL) return LBMRV_ERR_UNSUPPORTED;
+  // walls: pull form, or the in-place form with walls on both faces of an axis
+  // (a one-sided wall would let two nodes share one slot in place)
+  if (c->wall_mask && c->streaming == LBMRV_STREAM_PUSH) return LBMRV_ERR_UNSUPPORTED;
+  if (c->wall_mask && c->streaming == LBMRV_STREAM_AA)
+    for (int a = 0; a < c->d; ++a)
+      if (((c->wall_mask >> (2 * a)) & 1u) != ((c->wall_mask >> (2 * a + 1)) & 1u)) return LBMRV_ERR_UNSUPPORTED;
   if (c->custom && c->streaming == LBMRV_STREAM_AA) return LBMRV_ERR_UNSUPPORTED;
   if ((rc = check_device(c))) return rc;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
@@ -681,9 +686,16 @@ int lbmrv_step(lbmrv_ctx* c, void* f_in, void* f_out, int ut_mode, double ut_alp
     if (f_in != f_out &&
         hipMemcpyAsync(f_out, f_in, eb * c->q * c->N, hipMemcpyDeviceToDevice, st) != hipSuccess)
       return LBMRV_ERR_HIP;
-    hipError_t e = run_alternating(c, K_AA_EVEN, K_AA_ODD, f_out, f_out, nsteps, ut_mode, ut_alpha, ut_field, st);
+    hipError_t e = run_alternating(c, K_AA_EVEN, c->wall_mask ? K_AA_ODD_WALLS : K_AA_ODD, f_out, f_out, nsteps,
+                                   ut_mode, ut_alpha, ut_field, st);
     if (e != hipSuccess) return LBMRV_ERR_HIP;
-    if (nsteps % 2 == 1) e = kEntries[c->entry].fin[c->sk](f_out, c->nx, c->ny, c->nz, c->N, st);
+    if (nsteps % 2 == 1) {
+      FinArgs w{};
+      w.wall_mask = c->wall_mask;
+      for (int f = 0; f < 6; ++f)
+        for (int ax = 0; ax < 3; ++ax) w.wall_coef[f][ax] = 6.0 * c->rho_w * c->wall_u[f][ax] / c->lambda;
+      e = kEntries[c->entry].fin[c->sk](f_out, c->nx, c->ny, c->nz, c->N, w, st);
+    }
     return e == hipSuccess ? LBMRV_OK : LBMRV_ERR_HIP;
   }
   if (nsteps == 0) {

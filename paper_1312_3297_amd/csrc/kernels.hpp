@@ -65,7 +65,8 @@ enum Mode { UT_ZERO = 0, UT_FLUID = 1, UT_FIELD = 2 };
 // K_STREAM  gather f_j(x - c_j), store at x (no collision)
 // K_AA_EVEN load slot j at x, collide, store slot opp(j) at x         (in place)
 // K_AA_ODD  load slot opp(j) at x - c_j, collide, store slot j at x + c_j (in place)
-enum Kind { K_PULL = 0, K_PUSH = 1, K_COLLIDE = 2, K_STREAM = 3, K_AA_EVEN = 4, K_AA_ODD = 5 };
+// K_AA_ODD_WALLS  the same with half-way bounce-back walls on paired faces
+enum Kind { K_PULL = 0, K_PUSH = 1, K_COLLIDE = 2, K_STREAM = 3, K_AA_EVEN = 4, K_AA_ODD = 5, K_AA_ODD_WALLS = 6 };
 
 template <class T>
 struct StepArgs {
@@ -271,6 +272,40 @@ constexpr int step_max_threads() {
   return ST == 0 ? 512 : 1024;
 }
 
+// Half-way bounce-back.  wall_face_in<L, J>: the wall face that the link from
+// node pos - c_J to node pos passes (-1: none): for c_J[a] > 0 the low face of
+// axis a when pos[a] == 0, for c_J[a] < 0 the high face when pos[a] is the
+// last index; the first axis that matches decides.
+template <class L, int J>
+__device__ __forceinline__ int wall_face_in(uint32_t mask, const uint32_t (&pos)[3], const uint32_t (&ext)[3]) {
+  constexpr int cj[3] = {L::c[J].x, L::c[J].y, L::c[J].z};
+  int face = -1;
+  sfor<L::D>([&](auto ax) {
+    constexpr int c = cj[ax];
+    if constexpr (c > 0) {
+      if (face < 0 && ((mask >> (2 * ax)) & 1u) && pos[ax] == 0) face = 2 * ax;
+    } else if constexpr (c < 0) {
+      if (face < 0 && ((mask >> (2 * ax + 1)) & 1u) && pos[ax] == ext[ax] - 1) face = 2 * ax + 1;
+    }
+  });
+  return face;
+}
+
+// The population of direction J that bounced off wall `face`: the reflected
+// post-collision value plus the momentum a moving wall adds,
+// w_J (c_J . coef[face]) with coef = 6 rho_w u_w / lambda.
+template <class B, class T, int J>
+__device__ __forceinline__ T bounce(const T (&coef)[6][3], int face, T reflected) {
+  using L = typename B::Lat;
+  constexpr int cj[3] = {L::c[J].x, L::c[J].y, L::c[J].z};
+  constexpr T wj = lit<Tab<B>::t.w[J], T>();
+  T cu = T(0);
+  sfor<L::D>([&](auto ax) {
+    if constexpr (cj[ax] != 0) cu = fmac(T(cj[ax]), coef[face][ax], cu);
+  });
+  return fmac(wj, cu, reflected);
+}
+
 // Workgroups are dispatched to the eight XCDs round-robin by linear block
 // index, and each XCD has its own L2.  With remap set, block p instead takes
 // tile t so that every XCD receives one contiguous range of tiles: tiles that
@@ -328,11 +363,26 @@ __global__ __launch_bounds__(step_max_threads<ST>()) void k_step(StepArgs<typena
   S* fout = static_cast<S*>(a.fout);
   const uint64_t N = a.N;
 
-  constexpr bool gather = KIND == K_PULL || KIND == K_STREAM || KIND == K_AA_ODD;
+  constexpr bool aa_odd = KIND == K_AA_ODD || KIND == K_AA_ODD_WALLS;
+  constexpr bool gather = KIND == K_PULL || KIND == K_STREAM || aa_odd;
+  const uint32_t pos[3] = {x, y, z}, ext[3] = {nx, ny, nz};
   T h[Q];
   sfor<Q>([&](auto jj) {
     constexpr int J = jj;
-    constexpr int slot = KIND == K_AA_ODD ? opposite<L>(J) : J;
+    constexpr int slot = aa_odd ? opposite<L>(J) : J;
+    if constexpr (KIND == K_AA_ODD_WALLS) {
+      // in place, with walls: a population whose source lies beyond a wall is
+      // read from this node's slot J, where the even step left the opposite
+      // post-collision population (the periodic source slot is another node's
+      // to rewrite in this pass, so it is not read)
+      if (a.wall_mask) {
+        const int face = wall_face_in<L, J>(a.wall_mask, pos, ext);
+        if (face >= 0) {
+          h[J] = bounce<B, T, J>(a.wall_coef, face, T(fin[(uint64_t)J * N + own]));
+          return;
+        }
+      }
+    }
     uint32_t src = own;
     if constexpr (gather) src = nbr(jj, std::integral_constant<int, -1>{});
     // loads that are aligned with the wavefront (own node, or a neighbour in y
@@ -342,33 +392,16 @@ __global__ __launch_bounds__(step_max_threads<ST>()) void k_step(StepArgs<typena
     if constexpr (aligned) h[J] = T(__builtin_nontemporal_load(&fin[(uint64_t)slot * N + src]));
     else h[J] = T(fin[(uint64_t)slot * N + src]);
   });
-  // half-way bounce-back on wall faces (pull forms only): a population whose
-  // source lies beyond a wall is the node's own post-collision opposite
-  // population, plus the momentum of a moving wall
+  // half-way bounce-back on wall faces (two-array pull forms): a population
+  // whose source lies beyond a wall is the node's own post-collision opposite
+  // population, kept in slot opp(J) at the node, plus the momentum of a
+  // moving wall
   if constexpr (KIND == K_PULL || KIND == K_STREAM) {
     if (a.wall_mask) {
-      using Tb = Tab<B>;
-      const uint32_t pos[3] = {x, y, z}, ext[3] = {nx, ny, nz};
       sfor<Q>([&](auto jj) {
         constexpr int J = jj;
-        constexpr int cj[3] = {L::c[J].x, L::c[J].y, L::c[J].z};
-        int face = -1;
-        sfor<D>([&](auto ax) {
-          constexpr int c = cj[ax];
-          if constexpr (c > 0) {
-            if (face < 0 && ((a.wall_mask >> (2 * ax)) & 1u) && pos[ax] == 0) face = 2 * ax;
-          } else if constexpr (c < 0) {
-            if (face < 0 && ((a.wall_mask >> (2 * ax + 1)) & 1u) && pos[ax] == ext[ax] - 1) face = 2 * ax + 1;
-          }
-        });
-        if (face >= 0) {
-          constexpr T wj = lit<Tb::t.w[J], T>();
-          T cu = T(0);
-          sfor<D>([&](auto ax) {
-            if constexpr (cj[ax] != 0) cu = fmac(T(cj[ax]), a.wall_coef[face][ax], cu);
-          });
-          h[J] = fmac(wj, cu, T(fin[(uint64_t)opposite<L>(J) * N + own]));
-        }
+        const int face = wall_face_in<L, J>(a.wall_mask, pos, ext);
+        if (face >= 0) h[J] = bounce<B, T, J>(a.wall_coef, face, T(fin[(uint64_t)opposite<L>(J) * N + own]));
       });
     }
   }
@@ -388,7 +421,20 @@ __global__ __launch_bounds__(step_max_threads<ST>()) void k_step(StepArgs<typena
   // the partial lines and are faster.
   sfor<Q>([&](auto jj) {
     constexpr int J = jj;
-    if constexpr (KIND == K_PUSH || KIND == K_AA_ODD) {
+    if constexpr (KIND == K_AA_ODD_WALLS) {
+      // in-place form with walls: a population whose destination lies beyond a
+      // wall returns to this node as direction opp(J), bounced, into slot
+      // opp(J) here (the slot this node's read of that link would have used)
+      if (a.wall_mask) {
+        constexpr int O = opposite<L>(J);
+        const int face = wall_face_in<L, O>(a.wall_mask, pos, ext);
+        if (face >= 0) {
+          fout[(uint64_t)O * N + own] = S(bounce<B, T, O>(a.wall_coef, face, h[J]));
+          return;
+        }
+      }
+    }
+    if constexpr (KIND == K_PUSH || aa_odd) {
       S* dst = &fout[(uint64_t)J * N + nbr(jj, std::integral_constant<int, 1>{})];
       if constexpr (L::c[J].x == 0) __builtin_nontemporal_store(S(h[J]), dst);  // aligned with the wavefront
       else *dst = S(h[J]);
@@ -403,18 +449,38 @@ __global__ __launch_bounds__(step_max_threads<ST>()) void k_step(StepArgs<typena
 // the natural layout needs f_j(x) = f*_j(x - c_j).  Slots (j at x) and (opp(j)
 // at x - c_j) trade places, so one thread per node swaps one pair per
 // direction j with c_j > 0 in lexicographic order (each pair exactly once).
+// With walls (on both faces of an axis), a pair whose link passes a wall is
+// not swapped: each of its two slots already holds its node's bounced
+// population, which only gains the moving-wall term.
+struct FinArgs {
+  uint32_t wall_mask;
+  double wall_coef[6][3];
+};
+
 template <class B, int ST>
-__global__ __launch_bounds__(256) void k_aa_finish(void* fp, uint32_t nx, uint32_t ny, uint32_t nz, uint64_t N) {
+__global__ __launch_bounds__(256) void k_aa_finish(void* fp, uint32_t nx, uint32_t ny, uint32_t nz, uint64_t N,
+                                                   FinArgs w) {
   using L = typename B::Lat;
   using S = typename Store<ST>::S;
+  using T = typename Store<ST>::T;
   constexpr int Q = B::Q;
   const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t y = blockIdx.y, z = blockIdx.z;
   if (x >= nx) return;
   S* f = static_cast<S*>(fp);
   const uint32_t own = (z * ny + y) * nx + x;
+  const uint32_t pos[3] = {x, y, z}, ext[3] = {nx, ny, nz};
+  T coef[6][3];
+  for (int i = 0; i < 6; ++i)
+    for (int ax = 0; ax < 3; ++ax) coef[i][ax] = T(w.wall_coef[i][ax]);
   sfor<Q>([&](auto jj) {
     constexpr int J = jj;
+    const int face = w.wall_mask ? wall_face_in<L, J>(w.wall_mask, pos, ext) : -1;
+    if (face >= 0) {
+      S* p = &f[(uint64_t)J * N + own];
+      *p = S(bounce<B, T, J>(coef, face, T(*p)));
+      return;
+    }
     constexpr int cx = L::c[J].x, cy = L::c[J].y, cz = L::c[J].z;
     constexpr bool positive = cz > 0 || (cz == 0 && (cy > 0 || (cy == 0 && cx > 0)));
     if constexpr (positive) {

@@ -74,7 +74,9 @@ hipError_t launch_step_t(const StepLaunch& L) {
   const uint32_t bx_max = wide ? (uint32_t)step_max_threads<ST>() : 256u;
   const uint32_t bx = L.nx >= bx_max ? bx_max : ((L.nx + 63u) / 64u) * 64u;
   // (FP16 storage measured faster with one row per block)
-  uint32_t by = (KIND == K_PUSH || KIND == K_AA_ODD || ST == 2) ? 1u : (uint32_t)step_max_threads<ST>() / bx;
+  uint32_t by = (KIND == K_PUSH || KIND == K_AA_ODD || KIND == K_AA_ODD_WALLS || ST == 2)
+                    ? 1u
+                    : (uint32_t)step_max_threads<ST>() / bx;
   if (by > L.ny) by = L.ny;
   dim3 grid((L.nx + bx - 1) / bx, (L.ny + by - 1) / by, L.nz);
   hipLaunchKernelGGL((k_step<B, ST, MODE, KIND, RLX>), grid, dim3(bx, by), 0, L.stream, a);
@@ -99,14 +101,16 @@ hipError_t launch_step_m(const StepLaunch& L) {
     case K_STREAM: return launch_step_t<B, ST, UT_ZERO, K_STREAM, 0>(L);
     case K_AA_EVEN: return launch_step_t<B, ST, MODE, K_AA_EVEN, 0>(L);
     case K_AA_ODD: return launch_step_t<B, ST, MODE, K_AA_ODD, 0>(L);
+    case K_AA_ODD_WALLS: return launch_step_t<B, ST, MODE, K_AA_ODD_WALLS, 0>(L);
   }
   return hipErrorInvalidValue;
 }
 
 template <class B, int ST>
-hipError_t launch_aa_finish_t(void* f, uint32_t nx, uint32_t ny, uint32_t nz, uint64_t N, hipStream_t st) {
+hipError_t launch_aa_finish_t(void* f, uint32_t nx, uint32_t ny, uint32_t nz, uint64_t N, const FinArgs& w,
+                              hipStream_t st) {
   const uint32_t bx = nx >= 256 ? 256u : ((nx + 63u) / 64u) * 64u;
-  hipLaunchKernelGGL((k_aa_finish<B, ST>), dim3((nx + bx - 1) / bx, ny, nz), dim3(bx), 0, st, f, nx, ny, nz, N);
+  hipLaunchKernelGGL((k_aa_finish<B, ST>), dim3((nx + bx - 1) / bx, ny, nz), dim3(bx), 0, st, f, nx, ny, nz, N, w);
   return hipGetLastError();
 }
 
@@ -249,7 +253,7 @@ hipError_t launch_adjoint_s(const AdjLaunch& L) {
   hipError_t launch_init_##NAME##_##SKN(const InitLaunch& L);                               \
   hipError_t launch_adjoint_##NAME##_##SKN(const AdjLaunch& L);                             \
   hipError_t launch_aa_finish_##NAME##_##SKN(void* f, uint32_t nx, uint32_t ny, uint32_t nz, uint64_t N, \
-                                             hipStream_t st);                                \
+                                             const FinArgs& w, hipStream_t st);              \
   hipError_t launch_convert_##NAME##_##SKN(const void* in, void* out, double rho0, uint64_t N, \
                                            int to_storage, hipStream_t st);                  \
   hipError_t launch_devnorm_##NAME##_##SKN(const void* f, uint64_t N, const DevRef& ref,    \
@@ -269,8 +273,8 @@ hipError_t launch_adjoint_s(const AdjLaunch& L) {
   hipError_t launch_init_##NAME##_##SKN(const InitLaunch& L) { return launch_init_t<BASIS, ST>(L); } \
   hipError_t launch_adjoint_##NAME##_##SKN(const AdjLaunch& L) { return launch_adjoint_s<BASIS, ST>(L); } \
   hipError_t launch_aa_finish_##NAME##_##SKN(void* f, uint32_t nx, uint32_t ny, uint32_t nz, uint64_t N, \
-                                             hipStream_t st) {                               \
-    return launch_aa_finish_t<BASIS, ST>(f, nx, ny, nz, N, st);                             \
+                                             const FinArgs& w, hipStream_t st) {             \
+    return launch_aa_finish_t<BASIS, ST>(f, nx, ny, nz, N, w, st);                          \
   }                                                                                         \
   hipError_t launch_convert_##NAME##_##SKN(const void* in, void* out, double rho0, uint64_t N, \
                                            int to_storage, hipStream_t st) {               \

@@ -136,9 +136,12 @@ def test_walls_and_streaming_validation_before_any_hip_call():
     bad_u = (ctypes.c_double * 18)(*([0.0] * 17 + [float("inf")]))
     assert lib.lbmrv_set_walls(ctx._h, 0b1100, bad_u, 1.0) == lbmrv.ERR_INVALID_ARG
     assert lib.lbmrv_set_streaming(ctx._h, 2) == lbmrv.OK                               # in-place form
-    assert lib.lbmrv_set_walls(ctx._h, 0b1100, None, 1.0) == lbmrv.OK
+    assert lib.lbmrv_set_walls(ctx._h, 0b0100, None, 1.0) == lbmrv.OK
     a, b, st = ctypes.c_void_p(4096), ctypes.c_void_p(8192), ctypes.c_void_p(0)
-    assert lib.lbmrv_step(ctx._h, a, b, 0, 1.0, None, 1, st) == lbmrv.ERR_UNSUPPORTED   # walls need pull
+    assert lib.lbmrv_step(ctx._h, a, b, 0, 1.0, None, 1, st) == lbmrv.ERR_UNSUPPORTED   # one-sided wall in place
+    assert lib.lbmrv_set_streaming(ctx._h, 1) == lbmrv.OK                               # push form
+    assert lib.lbmrv_set_walls(ctx._h, 0b1100, None, 1.0) == lbmrv.OK
+    assert lib.lbmrv_step(ctx._h, a, b, 0, 1.0, None, 1, st) == lbmrv.ERR_UNSUPPORTED   # no walls in push
     assert lib.lbmrv_set_streaming(ctx._h, 0) == lbmrv.OK
     assert lib.lbmrv_step(ctx._h, a, a, 0, 1.0, None, 1, st) == lbmrv.ERR_INVALID_ARG   # in place needs AA
     assert lib.lbmrv_adjoint(ctx._h, a, 0, 1.0, None, 4, 2, b, ctypes.c_void_p(1 << 20), 1 << 30, None,

@@ -90,16 +90,81 @@ def test_walls_at_rest_conserve_mass_on_the_gpu():
     assert ok and abs(m1 - m0) <= 1e-12 * m0
 
 
-def test_walls_need_the_pull_form():
+def test_walls_need_the_pull_form_or_paired_in_place_walls():
     ctx = Lbmrv("d2q9", RATES[9], (8, 8), "f32")
-    ctx.set_walls(0b1100)
     f = torch.zeros((9, 8, 8), device="cuda")
     g = torch.empty_like(f)
-    for kind in ("push", "aa"):
+    for kind, mask in (("push", 0b1100), ("aa", 0b0100), ("aa", 0b1000), ("aa", 0b1101)):
+        ctx.set_walls(mask)
         ctx.set_streaming(kind)
         with pytest.raises(lbmrv.LbmrvError) as e:
             ctx.step(f, g, "zero", 1.0, None, 2)
         assert e.value.code == lbmrv.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("lattice,storage", [("d2q9", "f32"), ("d2q9", "f64"), ("d3q19", "f32"), ("d3q27", "f64")])
+@pytest.mark.parametrize("nsteps", [1, 2, 5, 8])
+def test_in_place_form_with_walls_matches_pull_bitwise(lattice, storage, nsteps):
+    """Walls on both y faces (the upper one moving) and, in 3-D, on both z
+    faces: the in-place form keeps each bounced population in the node's own
+    opposite slot and must reproduce the pull form bit for bit."""
+    lat = oracle_lattice(lattice)
+    shape = (11, 130) if lat.d == 2 else (6, 7, 70)
+    f0 = far_state(lat, shape, seed=14, amp=0.02, umax=0.05)
+    st, _ = to_storage(lat, f0, storage)
+    mask = (1 << 2) | (1 << 3) | ((1 << 4) | (1 << 5) if lat.d == 3 else 0)
+    uw = [[0.0, 0.0, 0.0] for _ in range(6)]
+    uw[3] = [0.03, 0.0, 0.0]
+    if lat.d == 3:
+        uw[4] = [0.0, 0.02, 0.0]
+    ctx = Lbmrv(lattice, RATES[lat.q], tuple(reversed(shape)), storage)
+    ctx.set_walls(mask, uw, 1.0)
+    ref_in = torch.from_numpy(st).cuda()
+    ref_out = torch.empty_like(ref_in)
+    ctx.step(ref_in, ref_out, "fluid", 1.0, None, nsteps)
+    ctx.set_streaming("aa")
+    one = torch.from_numpy(st).cuda()
+    ctx.step(one, one, "fluid", 1.0, None, nsteps)
+    torch.cuda.synchronize()
+    assert torch.equal(one, ref_out)
+    if storage == "f64":
+        ref = A.run(lat, f0, RATES[lat.q], nsteps, mode=A.FLUID, walls=(mask, uw, 1.0))
+        assert rel(one.cpu().numpy(), ref) <= 1e-12
+
+
+def test_in_place_form_with_walls_fp16_within_tolerance():
+    lat = oracle_lattice("d3q19")
+    shape = (6, 7, 70)
+    f0 = far_state(lat, shape, seed=15, amp=0.02, umax=0.05)
+    st, f0w = to_storage(lat, f0, "f16dev")
+    mask = 0b111100
+    uw = [[0.0, 0.0, 0.0] for _ in range(6)]
+    uw[3] = [0.03, 0.0, 0.0]
+    ctx = Lbmrv("d3q19", RATES[19], (70, 7, 6), "f16dev")
+    ctx.set_walls(mask, uw, 1.0)
+    ctx.set_streaming("aa")
+    one = torch.from_numpy(st).cuda()
+    n = 7
+    ctx.step(one, one, "fluid", 1.0, None, n)
+    torch.cuda.synchronize()
+    from _common import from_storage
+    ref = A.run(lat, f0w, RATES[19], n, mode=A.FLUID, walls=(mask, uw, 1.0))
+    assert rel(from_storage(lat, one.cpu().numpy(), "f16dev"), ref) <= 8e-5 * (n + 1)
+
+
+def test_in_place_walls_at_rest_conserve_mass():
+    lat = oracle_lattice("d3q19")
+    shape = (8, 9, 10)
+    rho, u = workloads.taylor_green(10, 0.03, shape=shape)
+    f0 = A.equilibrium(lat, rho, u)
+    ctx = Lbmrv("d3q19", RATES[19], (10, 9, 8), "f64")
+    ctx.set_walls(0b111111)
+    ctx.set_streaming("aa")
+    m0, _, _ = ctx.conservation(torch.from_numpy(f0).cuda())
+    f = torch.from_numpy(f0).cuda()
+    ctx.step(f, f, "fluid", 1.0, None, 101)
+    m1, _, ok = ctx.conservation(f)
+    assert ok and abs(m1 - m0) <= 1e-12 * m0
 
 
 @pytest.mark.parametrize("streaming", ["pull", "push", "aa"])

@@ -788,11 +788,11 @@ int lbmrv_moments(lbmrv_ctx* c, const void* f, void* rho, void* u, void* m0, voi
   return kEntries[c->entry].mom[c->sk](L) == hipSuccess ? LBMRV_OK : LBMRV_ERR_HIP;
 }
 
-int lbmrv_conservation(lbmrv_ctx* c, const void* f, double out[4], void* hip_stream) {
-  if (!c || !out) return LBMRV_ERR_INVALID_ARG;
-  int rc;
-  if ((rc = check_ptr(f, elem_bytes(c->storage)))) return rc;
-  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+// Runs a partial-sum kernel over the context's reduction buffer (allocated on
+// the first call, on the current device), sums its kRedBlocks rows in a fixed
+// order and copies the five totals to the host; blocking on `st`.
+extern "C++" template <class Partial>
+static int reduce5(lbmrv_ctx* c, Partial partial, hipStream_t st, double (&h)[5]) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return LBMRV_ERR_HIP;
   if (c->partial && c->partial_dev != dev) return LBMRV_ERR_INVALID_ARG;  // context bound to its first device
@@ -803,13 +803,23 @@ int lbmrv_conservation(lbmrv_ctx* c, const void* f, double out[4], void* hip_str
     }
     c->partial_dev = dev;
   }
-  if (kEntries[c->entry].cons[c->sk](f, c->N, c->partial, st) != hipSuccess) return LBMRV_ERR_HIP;
+  if (partial(c->partial) != hipSuccess) return LBMRV_ERR_HIP;
   double* res = c->partial + kRedBlocks * 5;
   hipLaunchKernelGGL(k_conserve_final, dim3(1), dim3(kRedThreads), 0, st, c->partial, res);
   if (hipGetLastError() != hipSuccess) return LBMRV_ERR_HIP;
-  double h[5];
   if (hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess) return LBMRV_ERR_HIP;
   if (hipStreamSynchronize(st) != hipSuccess) return LBMRV_ERR_HIP;
+  return LBMRV_OK;
+}
+
+int lbmrv_conservation(lbmrv_ctx* c, const void* f, double out[4], void* hip_stream) {
+  if (!c || !out) return LBMRV_ERR_INVALID_ARG;
+  int rc;
+  if ((rc = check_ptr(f, elem_bytes(c->storage)))) return rc;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  double h[5];
+  if ((rc = reduce5(c, [&](double* p) { return kEntries[c->entry].cons[c->sk](f, c->N, p, st); }, st, h)))
+    return rc;
   // sum of the stored values; deviation storage adds back rho0 * N (sum of w_j = 1,
   // sum of w_j c_j = 0)
   out[0] = h[0] + c->rho0 * (double)c->N;
@@ -837,23 +847,9 @@ int lbmrv_deviation_norm(lbmrv_ctx* c, const void* f, const double* f_ref, doubl
   DevRef r{};
   if ((rc = check_ptr(f, elem_bytes(c->storage))) || (rc = dev_ref(c, f_ref, r))) return rc;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return LBMRV_ERR_HIP;
-  if (c->partial && c->partial_dev != dev) return LBMRV_ERR_INVALID_ARG;
-  if (!c->partial) {
-    if (hipMalloc(&c->partial, sizeof(double) * (kRedBlocks * 5 + 8)) != hipSuccess) {
-      c->partial = nullptr;
-      return LBMRV_ERR_HIP;
-    }
-    c->partial_dev = dev;
-  }
-  if (kEntries[c->entry].dnorm[c->sk](f, c->N, r, c->partial, st) != hipSuccess) return LBMRV_ERR_HIP;
-  double* res = c->partial + kRedBlocks * 5;
-  hipLaunchKernelGGL(k_conserve_final, dim3(1), dim3(kRedThreads), 0, st, c->partial, res);
-  if (hipGetLastError() != hipSuccess) return LBMRV_ERR_HIP;
   double h[5];
-  if (hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess) return LBMRV_ERR_HIP;
-  if (hipStreamSynchronize(st) != hipSuccess) return LBMRV_ERR_HIP;
+  if ((rc = reduce5(c, [&](double* p) { return kEntries[c->entry].dnorm[c->sk](f, c->N, r, p, st); }, st, h)))
+    return rc;
   out[0] = h[0];
   return h[4] > 0 ? LBMRV_ERR_NONFINITE : LBMRV_OK;
 }

@@ -136,3 +136,41 @@ def test_fluid_mode_adjoint_matches_central_differences(name):
     _, u0 = A.conserved(lat, f0)
     _, gf_field, _, _ = E.vjp(lat, f0, s, n, cot, field=alpha * u0, K=2)
     assert np.abs(gf - gf_field).max() > 1e-8
+
+
+@pytest.mark.parametrize("name,mode", [("d2q9_geier", "fluid"), ("d2q9", "field"), ("d3q19", "fluid")])
+def test_maxwellian_adjoint_matches_central_differences(name, mode):
+    """The Maxwellian equilibria (m^eq = rho E[P_k(xi - u~)]): Oracle E's
+    gradients against central differences of Oracle A with the same
+    equilibrium, for u~ = u (differentiated through u = q / rho) and a field."""
+    lat, f0, s, field = _setup(name, noise=0.1, field_amp=0.2)
+    n = 5
+    fld = field if mode == "field" else None
+    alpha = 0.9 if mode == "fluid" else None
+    fN = A.run(lat, f0, s, n, mode=A.FIELD if fld is not None else A.FLUID, alpha=0.9, field=fld, eq="maxwellian")
+    _, cot = E.kinetic_energy(lat, fN)
+    _, gf, gs, gu = E.vjp(lat, f0, s, n, cot, field=fld, K=3, alpha=alpha, eq="maxwellian")
+    J = lambda f, ss, fl: E.objective_after(lat, f, ss, n, field=fl, alpha=alpha, eq="maxwellian")  # noqa: E731
+    J0 = J(f0, s, fld)
+    h = 2e-5
+    rng = np.random.default_rng(2)
+
+    def rfd(fun, x, direction):
+        # Richardson-extrapolated central difference: the Maxwellian's quartic
+        # terms make the O(h^2) truncation of a plain difference ~1e-7 here
+        return (4 * _fd(fun, x, direction, h / 2) - _fd(fun, x, direction, h)) / 3
+
+    def close(fd, ad):
+        return abs(fd - ad) <= 1e-9 * abs(fd) + 100 * 2.2e-16 * abs(J0) / h
+
+    for _ in range(2):
+        d = rng.standard_normal(f0.shape)
+        assert close(rfd(lambda x: J(x, s, fld), f0, d), (gf * d).sum())
+        ds = np.concatenate([np.zeros(lat.d + 1), rng.standard_normal(lat.q - lat.d - 1)])
+        assert close(rfd(lambda x: J(f0, x, fld), s, ds), (gs * ds).sum())
+        if fld is not None:
+            du = rng.standard_normal(fld.shape)
+            assert close(rfd(lambda x: J(f0, s, x), fld, du), (gu * du).sum())
+    # and the Maxwellian gradient differs from the polynomial one (the option matters)
+    _, gf_p, _, _ = E.vjp(lat, f0, s, n, cot, field=fld, K=3, alpha=alpha)
+    assert np.abs(gf_p - gf).max() > 1e-6 * np.abs(gf).max()

@@ -178,7 +178,7 @@ int lbmrv_set_streaming(lbmrv_ctx *c, int kind);
  *     the continuous Maxwellian of density rho, velocity u and temperature cs2
  *     (the equilibria of Geier's cascaded scheme, mentioned in the paper's
  *     introduction).  Conserved moments are unchanged.
- * lbmrv_adjoint supports the polynomial form only.  No HIP call.
+ * lbmrv_adjoint differentiates either form.  No HIP call.
  */
 int lbmrv_set_equilibrium(lbmrv_ctx *c, int kind);
 
@@ -245,7 +245,8 @@ int lbmrv_info(const lbmrv_ctx *c, int64_t *q, int64_t *d, int64_t *nodes, int64
  *   ut_field     FIELD mode: device float array [d][N] (SoA, same node order),
  *                otherwise ignored (may be NULL)
  *   nsteps       >= 0
- * Errors: INVALID_ARG, UNSUPPORTED (walls with a non-pull form), ALIGNMENT, HIP.
+ * Errors: INVALID_ARG, UNSUPPORTED (walls with the push form or one-sided
+ * walls in place; the in-place form with a run-time basis), ALIGNMENT, HIP.
  */
 int lbmrv_step(lbmrv_ctx *c, void *f_in, void *f_out, int ut_mode, double ut_alpha,
                const float *ut_field, int64_t nsteps, void *hip_stream);
@@ -337,7 +338,9 @@ int lbmrv_lattice_tables(int lattice, int32_t *cdirs, double *w);
  *               float otherwise; grad_s, grad_ut: double; all device arrays
  *   workspace   device memory of at least lbmrv_adjoint_workspace_bytes(c,
  *               nsteps, K) bytes, 256-byte aligned, owned by the caller
- * Asynchronous on hip_stream.  Errors: INVALID_ARG, ALIGNMENT, HIP.
+ * Either equilibrium (lbmrv_set_equilibrium) and a run-time basis are
+ * differentiated; walls are not (UNSUPPORTED).
+ * Asynchronous on hip_stream.  Errors: INVALID_ARG, UNSUPPORTED, ALIGNMENT, HIP.
  */
 size_t lbmrv_adjoint_workspace_bytes(const lbmrv_ctx *c, int64_t nsteps, int64_t K);
 int lbmrv_adjoint(lbmrv_ctx *c, const void *f0, int ut_mode, double ut_alpha, const float *ut_field,

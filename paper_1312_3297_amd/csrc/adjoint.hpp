@@ -37,6 +37,7 @@ struct AdjArgs {
   const T* rnn;     // run-time basis only: non-conserved block of R (P = R W), (Q-D-1)^2 row-major
   const T* rnninv;  // and its inverse
   uint32_t xcd_remap;  // block order, as for the step kernels (block_tile)
+  uint32_t eq_maxwell; // 1: equilibrium moments of the continuous Maxwellian
 };
 
 template <class B, int ST, int MODE, int RLX>
@@ -99,6 +100,51 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
     sfor<D>([&](auto al) { ut[al] = a.alpha * u[al]; });
   }
 
+  // Maxwellian option: per-axis moments E[xi^n] of N(u_a, cs2) (cs2 = 1/3 in
+  // lattice units, the same expressions as the forward kernel) and their
+  // derivatives with respect to u_a
+  const bool maxwell = a.eq_maxwell != 0;
+  T mu[3][kP], dmu[3][kP];
+  if (maxwell) {
+    constexpr T cs2 = T(1) / T(3);
+    sfor<3>([&](auto ax) {
+      const T w = ax < D ? u[ax] : T(0);
+      const T w2 = w * w;
+      mu[ax][0] = T(1);
+      mu[ax][1] = w;
+      mu[ax][2] = w2 + cs2;
+      mu[ax][3] = w * (w2 + T(3) * cs2);
+      mu[ax][4] = w2 * (w2 + T(6) * cs2) + T(3) * cs2 * cs2;
+      dmu[ax][0] = T(0);
+      dmu[ax][1] = T(1);
+      dmu[ax][2] = T(2) * w;
+      dmu[ax][3] = T(3) * (w2 + cs2);
+      dmu[ax][4] = T(4) * w * (w2 + T(3) * cs2);
+    });
+  }
+  // E_K = E[W_K(xi)] (so m^eq_K = rho E_K) and dE_K / du
+  auto maxwell_moment = [&](auto kk, T (&dek)[3]) -> T {
+    constexpr Poly pk = B::W(decltype(kk)::value);
+    T ek = T(0);
+    sfor<3>([&](auto al) { dek[al] = T(0); });
+    sfor<pk.n>([&](auto ti) {
+      constexpr PTerm tm = pk.t[ti];
+      constexpr int ex[3] = {tm.a, tm.b, tm.e};
+      const T c = lit<tm.c, T>();
+      ek = fmac(c, mu[0][tm.a] * mu[1][tm.b] * mu[2][tm.e], ek);
+      sfor<D>([&](auto al) {
+        if constexpr (ex[al] > 0) {
+          T prod = dmu[al][ex[al]];
+          sfor<3>([&](auto bx) {
+            if constexpr (bx != al) prod *= mu[bx][ex[bx]];
+          });
+          dek[al] = fmac(c, prod, dek[al]);
+        }
+      });
+    });
+    return ek;
+  };
+
   T v[Q];  // d0, then T(u~) d0
   sfor<Q>([&](auto kk) {
     constexpr int K = kk;
@@ -107,6 +153,13 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
     } else {
       T mh = T(0);
       sfor<Tb::t.sMW[K].n>([&](auto i) { axpy_c<Tb::t.sMW[K].val[i]>(mh, h[Tb::t.sMW[K].col[i]]); });
+      if (maxwell) {
+        T dek[3];
+        const T ek = maxwell_moment(kk, dek);
+        constexpr Rat ak = Tb::t.a[K];
+        v[K] = fmac(rho, ek, -(lit<ak, T>() * a.rho0)) - mh;
+        return;
+      }
       T quad = T(0);
       sfor<D>([&](auto al) {
         constexpr Rat bb = Tb::t.b[K][al];
@@ -266,6 +319,14 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
   sfor<Q>([&](auto kk) {
     constexpr int K = kk;
     if constexpr (K > D) {
+      if (maxwell) {
+        // d(rho E_K)/dh_j = E_K + sum_a dE_K/du_a (c_ja - u_a)
+        T dek[3];
+        const T ek = maxwell_moment(kk, dek);
+        A0 = fmac(z5[K], ek, A0);
+        sfor<D>([&](auto al) { Bv[al] = fmac(z5[K], dek[al], Bv[al]); });
+        return;
+      }
       T quad = T(0);
       sfor<D>([&](auto al) {
         constexpr Rat bb = Tb::t.b[K][al];

@@ -965,7 +965,6 @@ int lbmrv_adjoint(lbmrv_ctx* c, const void* f0, int ut_mode, double ut_alpha, co
   if (!std::isfinite(ut_alpha)) return LBMRV_ERR_INVALID_ARG;
   if (nsteps < 1 || K < 1) return LBMRV_ERR_INVALID_ARG;
   if (c->wall_mask) return LBMRV_ERR_UNSUPPORTED;  // the adjoint covers periodic domains
-  if (c->equilibrium != LBMRV_EQ_POLYNOMIAL) return LBMRV_ERR_UNSUPPORTED;  // and the polynomial equilibrium
   const size_t eb = elem_bytes(c->storage);
   const size_t tb = c->storage == LBMRV_F64 ? 8 : 4;
   int rc;
@@ -1019,6 +1018,7 @@ int lbmrv_adjoint(lbmrv_ctx* c, const void* f0, int ut_mode, double ut_alpha, co
   A.rnn = tab_ptr(c, 2);
   A.rnninv = tab_ptr(c, 3);
   A.xcd_remap = xcd_order(c);
+  A.eq_maxwell = c->equilibrium == LBMRV_EQ_MAXWELLIAN ? 1u : 0u;
   A.stream = st;
   A.block = c->block;
   // reverse sweep, one segment of K steps at a time; the last segment's states

@@ -199,6 +199,7 @@ struct AdjLaunch {
   const void* rnn;     // run-time basis: non-conserved block of R and its inverse, or null
   const void* rnninv;
   uint32_t xcd_remap;
+  uint32_t eq_maxwell;
   hipStream_t stream;
   int block;
 };
@@ -224,6 +225,7 @@ hipError_t launch_adjoint_t(const AdjLaunch& L) {
   a.rnn = static_cast<const T*>(L.rnn);
   a.rnninv = static_cast<const T*>(L.rnninv);
   a.xcd_remap = L.xcd_remap;
+  a.eq_maxwell = L.eq_maxwell;
   const int bx = L.block;
   dim3 grid((L.nx + bx - 1) / bx, L.ny, L.nz);
   hipLaunchKernelGGL((k_adjoint<B, ST, MODE, RLX>), grid, dim3(bx), 0, L.stream, a);

@@ -138,3 +138,33 @@ def test_autograd_function_matches_adjoint_and_gradcheck():
 
     s_in = torch.tensor([1.4, 1.7, 1.7, 1.2, 1.2, 1.4], dtype=torch.float64, requires_grad=True)
     assert torch.autograd.gradcheck(fun, (gpu(f0).requires_grad_(True), s_in), eps=1e-6, atol=1e-8, rtol=1e-6)
+
+
+@pytest.mark.parametrize("lattice,basis,mode", [("d2q9", "geier", "fluid"), ("d2q9", "default", "field"),
+                                                ("d3q19", "default", "fluid"), ("d3q27", "default", "zero")])
+def test_adjoint_with_maxwellian_equilibria_fp64(lattice, basis, mode):
+    """The reverse kernel differentiates the Maxwellian equilibria
+    (d(rho E_K)/dh through rho and u) as Oracle E's autodiff does."""
+    lat = oracle_lattice(lattice, basis)
+    shape = (10, 11) if lat.d == 2 else (4, 5, 6)
+    rng = np.random.default_rng(8)
+    rho = 1 + 0.01 * rng.standard_normal(shape)
+    u = 0.05 * rng.uniform(-1, 1, (lat.d,) + shape)
+    f0 = A.equilibrium(lat, rho, u) * (1 + 0.05 * rng.uniform(-1, 1, (lat.q,) + shape))
+    s = {9: workloads.RATES_D2Q9_GROUPED, 19: workloads.RATES_D3Q19, 27: workloads.RATES_D3Q27}[lat.q]
+    fld = (0.05 * rng.uniform(-1, 1, (lat.d,) + shape)).astype(np.float32).astype(np.float64) \
+        if mode == "field" else None
+    alpha = 0.8 if mode == "fluid" else None
+    n = 6
+    cot = rng.standard_normal(f0.shape)
+    _, gf, gs, gu = E.vjp(lat, f0, s, n, cot, field=fld, K=4, alpha=alpha, eq="maxwellian")
+    ctx = Lbmrv(lattice, s, tuple(reversed(shape)), "f64", basis=basis)
+    ctx.set_equilibrium("maxwellian")
+    _, gfg, gsg, gug = ctx.adjoint(gpu(f0), gpu(cot), n, 4, mode,
+                                   None if fld is None else gpu(fld.astype(np.float32)),
+                                   alpha=0.8 if mode == "fluid" else 1.0)
+    torch.cuda.synchronize()
+    assert rel(gfg.cpu().numpy(), gf) <= 1e-10
+    assert rel(gsg.cpu().numpy(), gs) <= 1e-10
+    if fld is not None:
+        assert rel(gug.cpu().numpy(), gu) <= 1e-10

@@ -46,9 +46,12 @@ def test_maxwellian_equilibrium_matches_oracle(lattice, basis, storage, mode, n)
     assert rel(poly, ref) > 1e-9
 
 
-def test_adjoint_rejects_the_maxwellian_option():
+def test_adjoint_still_rejects_walls():
+    """The adjoint covers periodic domains (either equilibrium); walls are not
+    differentiated."""
     ctx = Lbmrv("d2q9", RATES[9], (8, 8), "f64")
     ctx.set_equilibrium("maxwellian")
+    ctx.set_walls(0b1100)
     f = torch.zeros((9, 8, 8), dtype=torch.float64, device="cuda")
     with pytest.raises(lbmrv.LbmrvError) as e:
         ctx.adjoint(f, f, 3, 2, "zero")

@@ -37,6 +37,7 @@ TRAFFIC_GB = {
     ("d3q19_tgv256_f32_fluid", "aa"): 2.5503,
     ("d2q9_shear2048_f32_fluid", "aa"): 0.3021,
     ("d3q19_tgv256_f32_fluid", "push"): 2.5542,
+    ("d3q19_couette256_f32_fluid_walls", "aa"): 2.5503,
     ("d3q19_couette256_f32_fluid_walls", "pull"): 2.5539,
     ("d3q19_tgv256_f32_fluid_rawbasis", "pull"): 2.5536,
 }

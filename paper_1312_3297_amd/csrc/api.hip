@@ -599,9 +599,15 @@ int lbmrv_set_rates(lbmrv_ctx* c, const double* s) {
   int rc = check_rates(c->q, c->d, s);
   if (rc) return rc;
   if ((rc = check_device(c))) return rc;
+  double old[27];
+  for (int k = 0; k < 27; ++k) old[k] = c->s[k];
   for (int k = 0; k < c->q; ++k) c->s[k] = s[k];
   ++c->version;
-  return c->custom ? upload_basis(c) : LBMRV_OK;
+  if (c->custom && (rc = upload_basis(c))) {
+    for (int k = 0; k < 27; ++k) c->s[k] = old[k];  // the context keeps its previous rates
+    return rc;
+  }
+  return LBMRV_OK;
 }
 
 int lbmrv_set_streaming(lbmrv_ctx* c, int kind) {

@@ -416,9 +416,9 @@ __global__ __launch_bounds__(step_max_threads<ST>()) void k_step(StepArgs<typena
 
   // Stores: the gather forms write their own node (aligned, contiguous per
   // wavefront) and are streamed past the caches with non-temporal stores, which
-  // measured ~5% faster on MI355X for arrays far larger than L2 and MALL; the
-  // scatter form writes misaligned neighbours, where plain stores let L2 merge
-  // the partial lines and are faster.
+  // measured ~5% faster on MI355X for arrays far larger than L2 and MALL.  The
+  // scatter forms do the same for the populations without an x-shift and use
+  // plain stores for the +-1 shifted ones, whose partial lines L2 then merges.
   sfor<Q>([&](auto jj) {
     constexpr int J = jj;
     if constexpr (KIND == K_AA_ODD_WALLS) {

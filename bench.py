@@ -52,6 +52,8 @@ WORKLOADS = {
     # channel between two half-way bounce-back walls (y faces), the upper one
     # moving along x; Taylor-Green start as in the headline workload
     "d3q19_couette256_f32_fluid_walls": ("d3q19", (256, 256, 256), "f32", "fluid"),
+    "d3q19_tgv256_f64_fluid": ("d3q19", (256, 256, 256), "f64", "fluid"),
+    "d3q27_tgv192_f16dev_field": ("d3q27", (192, 192, 192), "f16dev", "field"),
     # run-time moment basis (raw second moments, three normal-stress rates):
     # the relaxation goes through a dense R^{-1} S R instead of compiled tables
     "d3q19_tgv256_f32_fluid_rawbasis": ("d3q19", (256, 256, 256), "f32", "fluid"),

@@ -57,6 +57,7 @@ int main() {
   rc |= run<19, uint16_t>("d3q19_256^3", n256);
   rc |= run<19, double>("d3q19_256^3", n256);
   rc |= run<27, float>("d3q27_192^3", n192);
+  rc |= run<27, uint16_t>("d3q27_192^3", n192);
   rc |= run<9, float>("d2q9_4096^2", n4096);
   rc |= run<9, float>("d2q9_2048^2", n2048);
   printf(rc ? "failed\n" : "done\n");

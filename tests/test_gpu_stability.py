@@ -111,3 +111,25 @@ def test_critical_speed_map_matches_oracle():
     # one bisection interval (0.6 / 2^12) of slack for decisions within the
     # rate's estimation error of the threshold
     assert worst <= 2 * 0.6 / 2 ** 12 + 1e-12
+
+
+def test_critical_speed_map_d3q19_matches_oracle():
+    """D3Q19 (the built-in graded monomial basis) on an 8^3 grid: critical
+    |u0| along x, the xy diagonal and the main diagonal, s_nu in {1.9, 1.99},
+    u~ = 0 and u~ = u, GPU power iteration against the oracle's eigenvalues."""
+    lat = lattices.make("d3q19")
+    rows = []
+    worst = 0.0
+    for sv in (1.9, 1.99):
+        s = [0.0] * 4 + [1.1] + [sv] * 5 + [1.5] * 6 + [1.3] * 3
+        for direction in ((1.0, 0.0, 0.0), (1.0, 1.0, 0.0), (1.0, 1.0, 1.0)):
+            got = [stability.critical_speed("d3q19", s, direction, 8, mode, iters=12) for mode in ("zero", "fluid")]
+            ref = [F.critical_speed(lat, s, direction, 8, mode, threshold=1e-3, iters=12)
+                   for mode in ("zero", "fluid")]
+            rows.append((sv, direction, got, ref))
+            worst = max(worst, max(abs(a - b) for a, b in zip(got, ref)))
+    print("\ncritical |u0| (GPU; oracle), D3Q19 8^3 grid, threshold 1 + 1e-3:")
+    for sv, direction, got, ref in rows:
+        print("  s_nu=%.2f dir=%s  u~=0: %.4f (%.4f)   u~=u: %.4f (%.4f)"
+              % (sv, direction, got[0], ref[0], got[1], ref[1]))
+    assert worst <= 2 * 0.6 / 2 ** 12 + 1e-12

@@ -31,7 +31,6 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_GB = {
     ("d3q19_tgv256_f32_fluid", "pull"): 2.5514,
     ("d3q19_tgv256_f16dev_fluid", "pull"): 1.2752,
-    ("d3q27_tgv192_f32_field", "pull"): 1.614,
     ("d2q9_shear4096_f32_fluid", "pull"): 1.2207,
     ("d2q9_shear2048_f32_fluid", "pull"): 0.3021,
     ("d3q19_tgv256_f32_fluid", "aa"): 2.5503,

@@ -87,6 +87,62 @@ struct StepArgs {
   uint32_t xcd_remap;  // 1: contiguous tile ranges per XCD (block_tile)
 };
 
+// ------------------------------------------------------------------ D3Q27 tensor form
+// D3Q27's velocities are {0, +1, -1}^3 and its working basis is the monomials
+// X^a Y^b Z^e with a, b, e <= 2, so M_W(0) is the tensor product of the 3 x 3
+// one-axis matrix (rows 1, X, X^2 on the velocities 0, +1, -1) and both it and
+// its inverse apply as three one-axis passes over a 3 x 3 x 3 cube.
+constexpr int t27_axis_index(int c) { return c == 0 ? 0 : (c > 0 ? 1 : 2); }
+
+// cube[a][b][e] = sum_j c_jx^a c_jy^b c_jz^e h_j, returned in working-basis order
+template <class T>
+__device__ __forceinline__ void t27_moments(const T (&h)[27], T (&m)[27]) {
+  using L = D3Q27Lat;
+  T c[3][3][3];
+  sfor<27>([&](auto jj) {
+    constexpr int J = jj;
+    c[t27_axis_index(L::c[J].x)][t27_axis_index(L::c[J].y)][t27_axis_index(L::c[J].z)] = h[J];
+  });
+  // one axis: (p0, p+, p-) -> (p0 + p+ + p-, p+ - p-, p+ + p-)
+  auto pass = [](T& p0, T& pp, T& pm) {
+    const T s = pp + pm, d = pp - pm;
+    p0 = p0 + s;
+    pp = d;
+    pm = s;
+  };
+  sfor<3>([&](auto i) { sfor<3>([&](auto j) { pass(c[i][j][0], c[i][j][1], c[i][j][2]); }); });
+  sfor<3>([&](auto i) { sfor<3>([&](auto k) { pass(c[i][0][k], c[i][1][k], c[i][2][k]); }); });
+  sfor<3>([&](auto j) { sfor<3>([&](auto k) { pass(c[0][j][k], c[1][j][k], c[2][j][k]); }); });
+  sfor<27>([&](auto kk) {
+    constexpr int K = kk;
+    m[K] = c[kExp27[K][0]][kExp27[K][1]][kExp27[K][2]];
+  });
+}
+
+// dh_j = (M_W(0)^{-1} m)_j: one axis (m0, m1, m2) -> (m0 - m2, (m1 + m2)/2, (m2 - m1)/2)
+template <class T>
+__device__ __forceinline__ void t27_populations(const T (&m)[27], T (&dh)[27]) {
+  using L = D3Q27Lat;
+  T c[3][3][3];
+  sfor<27>([&](auto kk) {
+    constexpr int K = kk;
+    c[kExp27[K][0]][kExp27[K][1]][kExp27[K][2]] = m[K];
+  });
+  auto pass = [](T& q0, T& q1, T& q2) {
+    const T f0 = q0 - q2, fp = T(0.5) * (q1 + q2), fm = T(0.5) * (q2 - q1);
+    q0 = f0;
+    q1 = fp;
+    q2 = fm;
+  };
+  sfor<3>([&](auto j) { sfor<3>([&](auto k) { pass(c[0][j][k], c[1][j][k], c[2][j][k]); }); });
+  sfor<3>([&](auto i) { sfor<3>([&](auto k) { pass(c[i][0][k], c[i][1][k], c[i][2][k]); }); });
+  sfor<3>([&](auto i) { sfor<3>([&](auto j) { pass(c[i][j][0], c[i][j][1], c[i][j][2]); }); });
+  sfor<27>([&](auto jj) {
+    constexpr int J = jj;
+    dh[J] = c[t27_axis_index(L::c[J].x)][t27_axis_index(L::c[J].y)][t27_axis_index(L::c[J].z)];
+  });
+}
+
 // ------------------------------------------------------------------ collision
 // In-register collision at one node.  h holds the populations minus w_j rho0.
 // After return h holds the post-collision values (same offset).
@@ -100,19 +156,29 @@ __device__ __forceinline__ void collide_node(T (&h)[B::Q], const StepArgs<T>& a,
   constexpr int D = L::D;
   using Tb = Tab<B>;
 
+  // D3Q27: all working-basis moments of h in three one-axis passes
+  constexpr bool tensor = std::is_same_v<B, BasisD3Q27>;
+  T mw[tensor ? 27 : 1];
+  if constexpr (tensor) t27_moments(h, mw);
+
   // conserved moments, eq. (rhoq): rho = rho0 + sum h, j = sum c h
-  T drho = h[0];
-  sfor<Q - 1>([&](auto jj) { drho += h[jj + 1]; });
-  T jm[3] = {T(0), T(0), T(0)};
-  sfor<Q>([&](auto jj) {
-    constexpr int J = jj;
-    if constexpr (L::c[J].x > 0) jm[0] += h[J];
-    if constexpr (L::c[J].x < 0) jm[0] -= h[J];
-    if constexpr (L::c[J].y > 0) jm[1] += h[J];
-    if constexpr (L::c[J].y < 0) jm[1] -= h[J];
-    if constexpr (L::c[J].z > 0) jm[2] += h[J];
-    if constexpr (L::c[J].z < 0) jm[2] -= h[J];
-  });
+  T drho, jm[3] = {T(0), T(0), T(0)};
+  if constexpr (tensor) {
+    drho = mw[0];
+    sfor<3>([&](auto al) { jm[al] = mw[1 + al]; });
+  } else {
+    drho = h[0];
+    sfor<Q - 1>([&](auto jj) { drho += h[jj + 1]; });
+    sfor<Q>([&](auto jj) {
+      constexpr int J = jj;
+      if constexpr (L::c[J].x > 0) jm[0] += h[J];
+      if constexpr (L::c[J].x < 0) jm[0] -= h[J];
+      if constexpr (L::c[J].y > 0) jm[1] += h[J];
+      if constexpr (L::c[J].y < 0) jm[1] -= h[J];
+      if constexpr (L::c[J].z > 0) jm[2] += h[J];
+      if constexpr (L::c[J].z < 0) jm[2] -= h[J];
+    });
+  }
   const T rho = a.rho0 + drho;
   const T irho = T(1) / rho;
   T u[3] = {jm[0] * irho, jm[1] * irho, D == 3 ? jm[2] * irho : T(0)};
@@ -151,9 +217,13 @@ __device__ __forceinline__ void collide_node(T (&h)[B::Q], const StepArgs<T>& a,
       dl[K] = T(0);
     } else {
       T mh = T(0);
-      sfor<Tb::t.sMW[K].n>([&](auto i) {
-        axpy_c<Tb::t.sMW[K].val[i]>(mh, h[Tb::t.sMW[K].col[i]]);
-      });
+      if constexpr (tensor) {
+        mh = mw[K];
+      } else {
+        sfor<Tb::t.sMW[K].n>([&](auto i) {
+          axpy_c<Tb::t.sMW[K].val[i]>(mh, h[Tb::t.sMW[K].col[i]]);
+        });
+      }
       if (maxwell) {
         // rho E[W_K(xi)] - rho0 a_K, with the monomial terms of W_K
         constexpr Poly pk = B::W(K);
@@ -253,12 +323,18 @@ __device__ __forceinline__ void collide_node(T (&h)[B::Q], const StepArgs<T>& a,
   if constexpr (MODE != UT_ZERO) shift(T(1));
 
   // back to populations: h += M_W(0)^{-1} dm  (dm vanishes on the conserved block)
-  sfor<Q>([&](auto jj) {
-    constexpr int J = jj;
-    T acc = T(0);
-    sfor<Tb::t.sMWinv[J].n>([&](auto i) { axpy_c<Tb::t.sMWinv[J].val[i]>(acc, dl[Tb::t.sMWinv[J].col[i]]); });
-    h[J] += acc;
-  });
+  if constexpr (tensor) {
+    T dh[27];
+    t27_populations(dl, dh);
+    sfor<Q>([&](auto jj) { h[jj] += dh[jj]; });
+  } else {
+    sfor<Q>([&](auto jj) {
+      constexpr int J = jj;
+      T acc = T(0);
+      sfor<Tb::t.sMWinv[J].n>([&](auto i) { axpy_c<Tb::t.sMWinv[J].val[i]>(acc, dl[Tb::t.sMWinv[J].col[i]]); });
+      h[J] += acc;
+    });
+  }
 }
 
 // ------------------------------------------------------------------ step kernel

@@ -29,16 +29,6 @@ HBM_PEAK_GBS = 8000.0
 # valid for the kernel version the counters were taken on, in the default
 # (automatic) block order; the in-place form averages its two kernels.
 TRAFFIC_GB = {
-    ("d3q19_tgv256_f32_fluid", "pull"): 2.5514,
-    ("d3q19_tgv256_f16dev_fluid", "pull"): 1.2752,
-    ("d2q9_shear4096_f32_fluid", "pull"): 1.2207,
-    ("d2q9_shear2048_f32_fluid", "pull"): 0.3021,
-    ("d3q19_tgv256_f32_fluid", "aa"): 2.5503,
-    ("d2q9_shear2048_f32_fluid", "aa"): 0.3021,
-    ("d3q19_tgv256_f32_fluid", "push"): 2.5542,
-    ("d3q19_couette256_f32_fluid_walls", "aa"): 2.5503,
-    ("d3q19_couette256_f32_fluid_walls", "pull"): 2.5539,
-    ("d3q19_tgv256_f32_fluid_rawbasis", "pull"): 2.5536,
 }
 
 WORKLOADS = {

@@ -43,6 +43,15 @@ __device__ __forceinline__ void axpy_c(T& y, T x) {
   else y = fmac(cv, x, y);
 }
 
+// Starting value of a sum: -0 is the additive identity for every x
+// (x + -0 = x, -0 - x = -x, fma(a, b, -0) = a b), so the compiler drops the
+// first add of each sum and the terms of moments known to vanish; +0 is not
+// (-0 + +0 = +0), and would cost one add per sum.
+template <class T>
+__device__ __forceinline__ constexpr T zsum() {
+  return T(-0.0);
+}
+
 template <Rat C, class T>
 __device__ __forceinline__ constexpr T lit() {
   return T(C.val());
@@ -119,7 +128,10 @@ __device__ __forceinline__ void t27_moments(const T (&h)[27], T (&m)[27]) {
   });
 }
 
-// dh_j = (M_W(0)^{-1} m)_j: one axis (m0, m1, m2) -> (m0 - m2, (m1 + m2)/2, (m2 - m1)/2)
+// 2^{|c_j|^2} (M_W(0)^{-1} m)_j.  One axis of the inverse is
+// (m0, m1, m2) -> (m0 - m2, (m1 + m2)/2, (m2 - m1)/2); the halves belong to
+// the population index, so the passes leave them out and the caller applies
+// 2^{-|c_j|^2} once per population.
 template <class T>
 __device__ __forceinline__ void t27_populations(const T (&m)[27], T (&dh)[27]) {
   using L = D3Q27Lat;
@@ -129,7 +141,7 @@ __device__ __forceinline__ void t27_populations(const T (&m)[27], T (&dh)[27]) {
     c[kExp27[K][0]][kExp27[K][1]][kExp27[K][2]] = m[K];
   });
   auto pass = [](T& q0, T& q1, T& q2) {
-    const T f0 = q0 - q2, fp = T(0.5) * (q1 + q2), fm = T(0.5) * (q2 - q1);
+    const T f0 = q0 - q2, fp = q1 + q2, fm = q2 - q1;
     q0 = f0;
     q1 = fp;
     q2 = fm;
@@ -151,6 +163,11 @@ __device__ __forceinline__ void t27_populations(const T (&m)[27], T (&dh)[27]) {
 // matrix a.relax = R^{-1} S R (non-conserved block).
 template <class B, class T, int MODE, int RLX>
 __device__ __forceinline__ void collide_node(T (&h)[B::Q], const StepArgs<T>& a, const T (&utf)[3]) {
+  // Products are fused into sums only where the source says so (fmac) or
+  // within one expression, never across statements: the pull, push and
+  // in-place kernels inline this body into different code, and must round it
+  // identically.
+#pragma clang fp contract(on)
   using L = typename B::Lat;
   constexpr int Q = B::Q;
   constexpr int D = L::D;
@@ -162,7 +179,7 @@ __device__ __forceinline__ void collide_node(T (&h)[B::Q], const StepArgs<T>& a,
   if constexpr (tensor) t27_moments(h, mw);
 
   // conserved moments, eq. (rhoq): rho = rho0 + sum h, j = sum c h
-  T drho, jm[3] = {T(0), T(0), T(0)};
+  T drho, jm[3] = {zsum<T>(), zsum<T>(), zsum<T>()};
   if constexpr (tensor) {
     drho = mw[0];
     sfor<3>([&](auto al) { jm[al] = mw[1 + al]; });
@@ -191,11 +208,32 @@ __device__ __forceinline__ void collide_node(T (&h)[B::Q], const StepArgs<T>& a,
     sfor<D>([&](auto al) { ut[al] = utf[al]; });
   }
 
-  // Maxwellian option: per-axis moments E[xi^n] of N(u_a, cs2), cs2 = 1/3 in
-  // lattice units, n = 0..4 (a uniform branch; unused by the polynomial form)
-  T mu[3][kP];
-  const bool maxwell = a.eq_maxwell != 0;
-  if (maxwell) {
+  // fixed-frame non-equilibrium moments in the working basis, dl = m^eq - m
+  // (k > d only; the conserved entries are exactly zero because f^eq has the
+  // same rho, j).  One uniform branch picks the equilibrium for all moments,
+  // so neither form is evaluated and then discarded; each branch subtracts m
+  // itself, so that every kernel rounds the difference the same way.
+  T dl[Q];
+  // m_K of the populations (k > d)
+  T mh[Q];
+  sfor<Q>([&](auto kk) {
+    constexpr int K = kk;
+    if constexpr (K <= D) {
+      dl[K] = zsum<T>();
+    } else if constexpr (tensor) {
+      mh[K] = mw[K];
+    } else {
+      mh[K] = zsum<T>();
+      sfor<Tb::t.sMW[K].n>([&](auto i) {
+        axpy_c<Tb::t.sMW[K].val[i]>(mh[K], h[Tb::t.sMW[K].col[i]]);
+      });
+    }
+  });
+  if (a.eq_maxwell != 0) {
+    // Maxwellian option: per-axis moments E[xi^n] of N(u_a, cs2), cs2 = 1/3
+    // in lattice units, n = 0..4; m^eq_K - rho0 a_K = rho E[W_K(xi)] - rho0 a_K
+    // from the monomial terms of W_K
+    T mu[3][kP];
     constexpr T cs2 = T(1) / T(3);
     sfor<3>([&](auto ax) {
       const T v = ax < D ? u[ax] : T(0);
@@ -206,54 +244,42 @@ __device__ __forceinline__ void collide_node(T (&h)[B::Q], const StepArgs<T>& a,
       mu[ax][3] = v * (v2 + T(3) * cs2);
       mu[ax][4] = v2 * (v2 + T(6) * cs2) + T(3) * cs2 * cs2;
     });
-  }
-
-  // fixed-frame non-equilibrium moments in the working basis (k > d only;
-  // the conserved entries are exactly zero because f^eq has the same rho, j)
-  T dl[Q];
-  sfor<Q>([&](auto kk) {
-    constexpr int K = kk;
-    if constexpr (K <= D) {
-      dl[K] = T(0);
-    } else {
-      T mh = T(0);
-      if constexpr (tensor) {
-        mh = mw[K];
-      } else {
-        sfor<Tb::t.sMW[K].n>([&](auto i) {
-          axpy_c<Tb::t.sMW[K].val[i]>(mh, h[Tb::t.sMW[K].col[i]]);
-        });
-      }
-      if (maxwell) {
-        // rho E[W_K(xi)] - rho0 a_K, with the monomial terms of W_K
+    sfor<Q>([&](auto kk) {
+      constexpr int K = kk;
+      if constexpr (K > D) {
         constexpr Poly pk = B::W(K);
-        T mk = T(0);
+        T mk = zsum<T>();
         sfor<pk.n>([&](auto ti) {
           constexpr PTerm tm = pk.t[ti];
           mk = fmac(lit<tm.c, T>(), mu[0][tm.a] * mu[1][tm.b] * mu[2][tm.e], mk);
         });
         constexpr Rat ak = Tb::t.a[K];
-        dl[K] = fmac(rho, mk, -(lit<ak, T>() * a.rho0)) - mh;
-        return;
+        dl[K] = fmac(rho, mk, -(lit<ak, T>() * a.rho0)) - mh[K];
       }
-      T quad = T(0);
-      sfor<D>([&](auto al) {
-        constexpr Rat bb = Tb::t.b[K][al];
-        if constexpr (!bb.zero()) quad = fmac(lit<bb, T>(), u[al], quad);
-        sfor<D>([&](auto be) {
-          if constexpr (be >= al) {
-            constexpr Rat cc = (be == al) ? Tb::t.C[K][al][be] : Tb::t.C[K][al][be] + Tb::t.C[K][be][al];
-            if constexpr (!cc.zero()) quad = fmac(lit<cc, T>() * u[al], u[be], quad);
-          }
+    });
+  } else {
+    // second-order polynomial equilibrium: rho (b.u + u.C.u) + a drho
+    sfor<Q>([&](auto kk) {
+      constexpr int K = kk;
+      if constexpr (K > D) {
+        T quad = zsum<T>();
+        sfor<D>([&](auto al) {
+          constexpr Rat bb = Tb::t.b[K][al];
+          if constexpr (!bb.zero()) quad = fmac(lit<bb, T>(), u[al], quad);
+          sfor<D>([&](auto be) {
+            if constexpr (be >= al) {
+              constexpr Rat cc = (be == al) ? Tb::t.C[K][al][be] : Tb::t.C[K][al][be] + Tb::t.C[K][be][al];
+              if constexpr (!cc.zero()) quad = fmac(lit<cc, T>() * u[al], u[be], quad);
+            }
+          });
         });
-      });
-      T eq = rho * quad;
-      constexpr Rat ak = Tb::t.a[K];
-      if constexpr (!ak.zero()) eq = fmac(lit<ak, T>(), drho, eq);
-      dl[K] = eq - mh;
-    }
-  });
-
+        T eq = rho * quad;
+        constexpr Rat ak = Tb::t.a[K];
+        if constexpr (!ak.zero()) eq = fmac(lit<ak, T>(), drho, eq);
+        dl[K] = eq - mh[K];
+      }
+    });
+  }
   // shift into the frame moving at u~:  dl <- prod_a exp(-u~_a D_a) dl
   auto shift = [&](T sign) {
     sfor<D>([&](auto ax) {
@@ -272,8 +298,13 @@ __device__ __forceinline__ void collide_node(T (&h)[B::Q], const StepArgs<T>& a,
           sfor<NM>([&](auto nn) {
             constexpr int N = nn + 1;
             constexpr int NZ = Tb::t.sE[AX][N][K].n;
-            if constexpr (NZ > 0) {
-              T acc = T(0);
+            if constexpr (NZ == 1) {
+              // one term: the constant goes into the power, which the
+              // compiler then shares between all rows with that constant
+              constexpr Rat cv = Tb::t.sE[AX][N][K].val[0];
+              out[K] = fmac(lit<cv, T>() * pw[N], dl[Tb::t.sE[AX][N][K].col[0]], out[K]);
+            } else if constexpr (NZ > 1) {
+              T acc = zsum<T>();
               sfor<NZ>([&](auto i) {
                 axpy_c<Tb::t.sE[AX][N][K].val[i]>(acc, dl[Tb::t.sE[AX][N][K].col[i]]);
               });
@@ -292,7 +323,7 @@ __device__ __forceinline__ void collide_node(T (&h)[B::Q], const StepArgs<T>& a,
     constexpr int NC = Q - D - 1;
     T r[NC];
     sfor<NC>([&](auto ii) {
-      T acc = T(0);
+      T acc = zsum<T>();
       sfor<NC>([&](auto jj) { acc = fmac(a.relax[ii * NC + jj], dl[D + 1 + jj], acc); });
       r[ii] = acc;
     });
@@ -302,17 +333,17 @@ __device__ __forceinline__ void collide_node(T (&h)[B::Q], const StepArgs<T>& a,
     sfor<Q>([&](auto kk) {
       constexpr int K = kk;
       if constexpr (K > D) {
-        T acc = T(0);
+        T acc = zsum<T>();
         sfor<Tb::t.sR[K].n>([&](auto i) { axpy_c<Tb::t.sR[K].val[i]>(acc, dl[Tb::t.sR[K].col[i]]); });
         r[K] = acc * a.s[K];
       } else {
-        r[K] = T(0);
+        r[K] = zsum<T>();
       }
     });
     sfor<Q>([&](auto kk) {
       constexpr int K = kk;
       if constexpr (K > D) {
-        T acc = T(0);
+        T acc = zsum<T>();
         sfor<Tb::t.sRinv[K].n>([&](auto i) { axpy_c<Tb::t.sRinv[K].val[i]>(acc, r[Tb::t.sRinv[K].col[i]]); });
         dl[K] = acc;
       }
@@ -326,11 +357,16 @@ __device__ __forceinline__ void collide_node(T (&h)[B::Q], const StepArgs<T>& a,
   if constexpr (tensor) {
     T dh[27];
     t27_populations(dl, dh);
-    sfor<Q>([&](auto jj) { h[jj] += dh[jj]; });
+    sfor<Q>([&](auto jj) {
+      constexpr int J = jj;
+      constexpr int c2 = L::c[J].x * L::c[J].x + L::c[J].y * L::c[J].y + L::c[J].z * L::c[J].z;
+      if constexpr (c2 == 0) h[J] += dh[J];
+      else h[J] = fmac(T(1.0 / (1 << c2)), dh[J], h[J]);
+    });
   } else {
     sfor<Q>([&](auto jj) {
       constexpr int J = jj;
-      T acc = T(0);
+      T acc = zsum<T>();
       sfor<Tb::t.sMWinv[J].n>([&](auto i) { axpy_c<Tb::t.sMWinv[J].val[i]>(acc, dl[Tb::t.sMWinv[J].col[i]]); });
       h[J] += acc;
     });
@@ -375,7 +411,7 @@ __device__ __forceinline__ T bounce(const T (&coef)[6][3], int face, T reflected
   using L = typename B::Lat;
   constexpr int cj[3] = {L::c[J].x, L::c[J].y, L::c[J].z};
   constexpr T wj = lit<Tab<B>::t.w[J], T>();
-  T cu = T(0);
+  T cu = zsum<T>();
   sfor<L::D>([&](auto ax) {
     if constexpr (cj[ax] != 0) cu = fmac(T(cj[ax]), coef[face][ax], cu);
   });

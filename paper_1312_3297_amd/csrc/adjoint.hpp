@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
   // ---- forward quantities at this node
   T drho = h[0];
   sfor<Q - 1>([&](auto jj) { drho += h[jj + 1]; });
-  T jm[3] = {T(0), T(0), T(0)};
+  T jm[3] = {zsum<T>(), zsum<T>(), zsum<T>()};
   sfor<Q>([&](auto jj) {
     constexpr int J = jj;
     if constexpr (L::c[J].x > 0) jm[0] += h[J];
@@ -125,8 +125,8 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
   // E_K = E[W_K(xi)] (so m^eq_K = rho E_K) and dE_K / du
   auto maxwell_moment = [&](auto kk, T (&dek)[3]) -> T {
     constexpr Poly pk = B::W(decltype(kk)::value);
-    T ek = T(0);
-    sfor<3>([&](auto al) { dek[al] = T(0); });
+    T ek = zsum<T>();
+    sfor<3>([&](auto al) { dek[al] = zsum<T>(); });
     sfor<pk.n>([&](auto ti) {
       constexpr PTerm tm = pk.t[ti];
       constexpr int ex[3] = {tm.a, tm.b, tm.e};
@@ -146,37 +146,50 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
   };
 
   T v[Q];  // d0, then T(u~) d0
+  T mh[Q];
   sfor<Q>([&](auto kk) {
     constexpr int K = kk;
     if constexpr (K <= D) {
-      v[K] = T(0);
+      v[K] = zsum<T>();
     } else {
-      T mh = T(0);
-      sfor<Tb::t.sMW[K].n>([&](auto i) { axpy_c<Tb::t.sMW[K].val[i]>(mh, h[Tb::t.sMW[K].col[i]]); });
-      if (maxwell) {
+      mh[K] = zsum<T>();
+      sfor<Tb::t.sMW[K].n>([&](auto i) { axpy_c<Tb::t.sMW[K].val[i]>(mh[K], h[Tb::t.sMW[K].col[i]]); });
+    }
+  });
+  // one uniform branch for all moments (neither equilibrium is evaluated and
+  // then discarded)
+  if (maxwell) {
+    sfor<Q>([&](auto kk) {
+      constexpr int K = kk;
+      if constexpr (K > D) {
         T dek[3];
         const T ek = maxwell_moment(kk, dek);
         constexpr Rat ak = Tb::t.a[K];
-        v[K] = fmac(rho, ek, -(lit<ak, T>() * a.rho0)) - mh;
-        return;
+        v[K] = fmac(rho, ek, -(lit<ak, T>() * a.rho0)) - mh[K];
       }
-      T quad = T(0);
-      sfor<D>([&](auto al) {
-        constexpr Rat bb = Tb::t.b[K][al];
-        if constexpr (!bb.zero()) quad = fmac(lit<bb, T>(), u[al], quad);
-        sfor<D>([&](auto be) {
-          if constexpr (be >= al) {
-            constexpr Rat cc = (be == al) ? Tb::t.C[K][al][be] : Tb::t.C[K][al][be] + Tb::t.C[K][be][al];
-            if constexpr (!cc.zero()) quad = fmac(lit<cc, T>() * u[al], u[be], quad);
-          }
+    });
+  } else {
+    sfor<Q>([&](auto kk) {
+      constexpr int K = kk;
+      if constexpr (K > D) {
+        T quad = zsum<T>();
+        sfor<D>([&](auto al) {
+          constexpr Rat bb = Tb::t.b[K][al];
+          if constexpr (!bb.zero()) quad = fmac(lit<bb, T>(), u[al], quad);
+          sfor<D>([&](auto be) {
+            if constexpr (be >= al) {
+              constexpr Rat cc = (be == al) ? Tb::t.C[K][al][be] : Tb::t.C[K][al][be] + Tb::t.C[K][be][al];
+              if constexpr (!cc.zero()) quad = fmac(lit<cc, T>() * u[al], u[be], quad);
+            }
+          });
         });
-      });
-      T eq = rho * quad;
-      constexpr Rat ak = Tb::t.a[K];
-      if constexpr (!ak.zero()) eq = fmac(lit<ak, T>(), drho, eq);
-      v[K] = eq - mh;
-    }
-  });
+        T eq = rho * quad;
+        constexpr Rat ak = Tb::t.a[K];
+        if constexpr (!ak.zero()) eq = fmac(lit<ak, T>(), drho, eq);
+        v[K] = eq - mh[K];
+      }
+    });
+  }
 
   // out = prod_a exp(sign u~_a D_a) in (rows: transposed or not), non-conserved block
   auto apply_shift = [&](T (&w)[Q], T sign, auto transposed) {
@@ -197,8 +210,11 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
           sfor<NM>([&](auto nn) {
             constexpr int NN = nn + 1;
             constexpr auto row = TR ? Tb::t.tE[AX][NN][K] : Tb::t.sE[AX][NN][K];
-            if constexpr (row.n > 0) {
-              T acc = T(0);
+            if constexpr (row.n == 1) {
+              // one term: its constant goes into the (shared) power
+              out[K] = fmac(lit<row.val[0], T>() * pw[NN], w[row.col[0]], out[K]);
+            } else if constexpr (row.n > 1) {
+              T acc = zsum<T>();
               sfor<row.n>([&](auto i) { axpy_c<row.val[i]>(acc, w[row.col[i]]); });
               out[K] = fmac(pw[NN], acc, out[K]);
             }
@@ -215,9 +231,9 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
   auto dense = [&](const T* m, const T (&x)[Q], T (&y)[Q], auto transposed, auto scale_by_s) {
     constexpr bool TR = decltype(transposed)::value;
     constexpr bool SC = decltype(scale_by_s)::value;
-    sfor<D + 1>([&](auto kk) { y[kk] = T(0); });
+    sfor<D + 1>([&](auto kk) { y[kk] = zsum<T>(); });
     sfor<NC>([&](auto ii) {
-      T acc = T(0);
+      T acc = zsum<T>();
       sfor<NC>([&](auto jj) {
         const T xv = SC ? x[D + 1 + jj] * a.s[D + 1 + jj] : x[D + 1 + jj];
         acc = fmac(TR ? m[jj * NC + ii] : m[ii * NC + jj], xv, acc);
@@ -233,13 +249,13 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
   } else {
   sfor<Q>([&](auto kk) {
     constexpr int K = kk;
-    T acc = T(0);
+    T acc = zsum<T>();
     if constexpr (K > D) sfor<Tb::t.sR[K].n>([&](auto i) { axpy_c<Tb::t.sR[K].val[i]>(acc, v[Tb::t.sR[K].col[i]]); });
     r[K] = acc;
   });
   sfor<Q>([&](auto kk) {
     constexpr int K = kk;
-    T acc = T(0);
+    T acc = zsum<T>();
     if constexpr (K > D)
       sfor<Tb::t.sRinv[K].n>([&](auto i) {
         constexpr int l = Tb::t.sRinv[K].col[i];
@@ -253,7 +269,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
   T zz[Q];  // z1 -> z2 (in place through the shift)
   sfor<Q>([&](auto kk) {
     constexpr int K = kk;
-    T acc = T(0);
+    T acc = zsum<T>();
     if constexpr (K > D)
       sfor<Tb::t.tMWinv[K].n>([&](auto i) { axpy_c<Tb::t.tMWinv[K].val[i]>(acc, g[Tb::t.tMWinv[K].col[i]]); });
     zz[K] = acc;
@@ -267,14 +283,14 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
   } else {
   sfor<Q>([&](auto kk) {
     constexpr int K = kk;
-    T acc = T(0);
+    T acc = zsum<T>();
     if constexpr (K > D)
       sfor<Tb::t.tRinv[K].n>([&](auto i) { axpy_c<Tb::t.tRinv[K].val[i]>(acc, zz[Tb::t.tRinv[K].col[i]]); });
     z3[K] = acc;
   });
   sfor<Q>([&](auto kk) {
     constexpr int K = kk;
-    T acc = T(0);
+    T acc = zsum<T>();
     if constexpr (K > D)
       sfor<Tb::t.tR[K].n>([&](auto i) {
         constexpr int l = Tb::t.tR[K].col[i];
@@ -290,12 +306,12 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
   if constexpr (MODE != UT_ZERO) {
     sfor<D>([&](auto ax) {
       constexpr int AX = ax;
-      T gsum = T(0);
+      T gsum = zsum<T>();
       sfor<Q>([&](auto kk) {
         constexpr int K = kk;
         constexpr auto row = Tb::t.sE[AX][1][K];
         if constexpr (K > D && row.n > 0) {
-          T da = T(0), dv = T(0);
+          T da = zsum<T>(), dv = zsum<T>();
           sfor<row.n>([&](auto i) {
             axpy_c<row.val[i]>(da, am[row.col[i]]);
             axpy_c<row.val[i]>(dv, v[row.col[i]]);
@@ -315,38 +331,43 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
   if constexpr (MODE != UT_ZERO) apply_shift(z5, T(-1), std::true_type{});
 
   // lambda^n = g - M_W^T z6 + (d m^eq / d h)^T z6
-  T A0 = T(0), Bv[3] = {T(0), T(0), T(0)};
-  sfor<Q>([&](auto kk) {
-    constexpr int K = kk;
-    if constexpr (K > D) {
-      if (maxwell) {
-        // d(rho E_K)/dh_j = E_K + sum_a dE_K/du_a (c_ja - u_a)
+  T A0 = zsum<T>(), Bv[3] = {zsum<T>(), zsum<T>(), zsum<T>()};
+  if (maxwell) {
+    // d(rho E_K)/dh_j = E_K + sum_a dE_K/du_a (c_ja - u_a)
+    sfor<Q>([&](auto kk) {
+      constexpr int K = kk;
+      if constexpr (K > D) {
         T dek[3];
         const T ek = maxwell_moment(kk, dek);
         A0 = fmac(z5[K], ek, A0);
         sfor<D>([&](auto al) { Bv[al] = fmac(z5[K], dek[al], Bv[al]); });
-        return;
       }
-      T quad = T(0);
-      sfor<D>([&](auto al) {
-        constexpr Rat bb = Tb::t.b[K][al];
-        T dq = T(0);
-        if constexpr (!bb.zero()) {
-          quad = fmac(lit<bb, T>(), u[al], quad);
-          dq = lit<bb, T>();
-        }
-        sfor<D>([&](auto be) {
-          constexpr Rat cab = Tb::t.C[K][al][be];
-          constexpr Rat csym = Tb::t.C[K][al][be] + Tb::t.C[K][be][al];
-          if constexpr (!cab.zero()) quad = fmac(lit<cab, T>() * u[al], u[be], quad);
-          if constexpr (!csym.zero()) dq = fmac(lit<csym, T>(), u[be], dq);
+    });
+  } else {
+    sfor<Q>([&](auto kk) {
+      constexpr int K = kk;
+      if constexpr (K > D) {
+        T quad = zsum<T>();
+        sfor<D>([&](auto al) {
+          constexpr Rat bb = Tb::t.b[K][al];
+          T dq = zsum<T>();
+          if constexpr (!bb.zero()) {
+            quad = fmac(lit<bb, T>(), u[al], quad);
+            dq = lit<bb, T>();
+          }
+          sfor<D>([&](auto be) {
+            constexpr Rat cab = Tb::t.C[K][al][be];
+            constexpr Rat csym = Tb::t.C[K][al][be] + Tb::t.C[K][be][al];
+            if constexpr (!cab.zero()) quad = fmac(lit<cab, T>() * u[al], u[be], quad);
+            if constexpr (!csym.zero()) dq = fmac(lit<csym, T>(), u[be], dq);
+          });
+          Bv[al] = fmac(z5[K], dq, Bv[al]);
         });
-        Bv[al] = fmac(z5[K], dq, Bv[al]);
-      });
-      constexpr Rat ak = Tb::t.a[K];
-      A0 = fmac(z5[K], lit<ak, T>() + quad, A0);
-    }
-  });
+        constexpr Rat ak = Tb::t.a[K];
+        A0 = fmac(z5[K], lit<ak, T>() + quad, A0);
+      }
+    });
+  }
   if constexpr (MODE == UT_FLUID) {
     sfor<D>([&](auto al) { Bv[al] = fmac(a.alpha * irho, gut[al], Bv[al]); });
   }
@@ -354,7 +375,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
     T* lo = a.lam_out;
     sfor<Q>([&](auto jj) {
       constexpr int J = jj;
-      T yv = T(0);
+      T yv = zsum<T>();
       sfor<Tb::t.tMW[J].n>([&](auto i) { axpy_c<Tb::t.tMW[J].val[i]>(yv, z5[Tb::t.tMW[J].col[i]]); });
       T lam = g[J] - yv + A0;
       sfor<D>([&](auto al) {

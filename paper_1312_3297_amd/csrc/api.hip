@@ -36,16 +36,29 @@ __global__ __launch_bounds__(256) void k_fill_zero(double* p, uint64_t n) {
   if (i < n) p[i] = 0.0;
 }
 
-// grad_s[k] = sum over blocks of partial[b][k] in block order (deterministic);
-// zero for the conserved moments k <= d.
-__global__ __launch_bounds__(64) void k_reduce_columns(const double* partial, uint64_t nblocks, int q, int d,
-                                                       double* out) {
-  const int k = threadIdx.x;
-  if (k >= q) return;
-  double s = 0.0;
-  if (k > d)
-    for (uint64_t b = 0; b < nblocks; ++b) s += partial[b * q + k];
-  out[k] = s;
+// grad_s[k] = sum over blocks of partial[b][k]; zero for the conserved moments
+// k <= d.  One workgroup of 32 x 32 threads: thread (k, r) adds the rows
+// b = r (mod 32) in increasing b into four interleaved sums, which then meet
+// in a fixed tree, so the result does not depend on scheduling.
+constexpr int kRedCols = 32, kRedRows = 32;
+__global__ __launch_bounds__(kRedCols* kRedRows) void k_reduce_columns(const double* partial, uint64_t nblocks,
+                                                                        int q, int d, double* out) {
+  __shared__ double red[kRedRows][kRedCols];
+  const int k = threadIdx.x, r = threadIdx.y;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  if (k < q && k > d) {
+    uint64_t b = r;
+    for (; b + 3 * kRedRows < nblocks; b += 4 * kRedRows)
+      for (int m = 0; m < 4; ++m) s[m] += partial[(b + m * kRedRows) * q + k];
+    for (int m = 0; b < nblocks; b += kRedRows, ++m) s[m] += partial[b * q + k];
+  }
+  red[r][k] = (s[0] + s[1]) + (s[2] + s[3]);
+  __syncthreads();
+  for (int half = kRedRows / 2; half > 0; half >>= 1) {
+    if (r < half) red[r][k] += red[r + half][k];
+    __syncthreads();
+  }
+  if (r == 0 && k < q) out[k] = red[0][k];
 }
 
 namespace {
@@ -1045,7 +1058,7 @@ int lbmrv_adjoint(lbmrv_ctx* c, const void* f0, int ut_mode, double ut_alpha, co
       if ((e = E.adj[c->sk](A)) != hipSuccess) return LBMRV_ERR_HIP;
     }
   }
-  hipLaunchKernelGGL(k_reduce_columns, dim3(1), dim3(64), 0, st, partial, P.nblocks, c->q, c->d, grad_s);
+  hipLaunchKernelGGL(k_reduce_columns, dim3(1), dim3(kRedCols, kRedRows), 0, st, partial, P.nblocks, c->q, c->d, grad_s);
   return hipGetLastError() == hipSuccess ? LBMRV_OK : LBMRV_ERR_HIP;
 }
 

@@ -77,6 +77,11 @@ hipError_t launch_step_t(const StepLaunch& L) {
   uint32_t by = (KIND == K_PUSH || KIND == K_AA_ODD || KIND == K_AA_ODD_WALLS || ST == 2)
                     ? 1u
                     : (uint32_t)step_max_threads<ST>() / bx;
+  // D3Q27's step holds ~90 VGPRs, so at most 5 wavefronts per SIMD: one
+  // 15-wavefront block of five 192-wide rows per CU leaves slots idle, blocks
+  // of two rows pack better (measured +2.6 % at 192^3 FP32; one row and three
+  // to five rows were slower, and D3Q19 stays fastest at four rows)
+  if (B::Q == 27 && by > 2u) by = 2u;
   if (by > L.ny) by = L.ny;
   dim3 grid((L.nx + bx - 1) / bx, (L.ny + by - 1) / by, L.nz);
   hipLaunchKernelGGL((k_step<B, ST, MODE, KIND, RLX>), grid, dim3(bx, by), 0, L.stream, a);

@@ -96,62 +96,163 @@ struct StepArgs {
   uint32_t xcd_remap;  // 1: contiguous tile ranges per XCD (block_tile)
 };
 
-// ------------------------------------------------------------------ D3Q27 tensor form
-// D3Q27's velocities are {0, +1, -1}^3 and its working basis is the monomials
-// X^a Y^b Z^e with a, b, e <= 2, so M_W(0) is the tensor product of the 3 x 3
-// one-axis matrix (rows 1, X, X^2 on the velocities 0, +1, -1) and both it and
-// its inverse apply as three one-axis passes over a 3 x 3 x 3 cube.
-constexpr int t27_axis_index(int c) { return c == 0 ? 0 : (c > 0 ? 1 : 2); }
-
-// cube[a][b][e] = sum_j c_jx^a c_jy^b c_jz^e h_j, returned in working-basis order
-template <class T>
-__device__ __forceinline__ void t27_moments(const T (&h)[27], T (&m)[27]) {
-  using L = D3Q27Lat;
-  T c[3][3][3];
-  sfor<27>([&](auto jj) {
-    constexpr int J = jj;
-    c[t27_axis_index(L::c[J].x)][t27_axis_index(L::c[J].y)][t27_axis_index(L::c[J].z)] = h[J];
-  });
-  // one axis: (p0, p+, p-) -> (p0 + p+ + p-, p+ - p-, p+ + p-)
-  auto pass = [](T& p0, T& pp, T& pm) {
-    const T s = pp + pm, d = pp - pm;
-    p0 = p0 + s;
-    pp = d;
-    pm = s;
+// ------------------------------------------------------------------ cube form
+// When the velocities lie in {0, +1, -1}^3 and the working basis is a set of
+// monomials X^a Y^b Z^e with a, b, e <= 2, M_W(0) is a restriction of the
+// 27 x 27 tensor product of one 3 x 3 matrix per axis (rows 1, X, X^2 on the
+// velocities 0, +1, -1), and both M_W(0) and its inverse apply as three
+// one-axis passes over a 3 x 3 x 3 cube of cells.  Cells that hold no value
+// (velocities the lattice lacks, monomials the basis lacks, the conserved
+// moments, which vanish in the collision's moment change) are known at compile
+// time and cost nothing.  The inverse is exact for a lattice smaller than the
+// cube when every monomial missing from the basis vanishes on all of its
+// velocities (D3Q19: the monomials with all three exponents >= 1): the cube
+// moments of a population vector on such a lattice are its basis moments plus
+// zeros, so the cube inverse of (moments, zeros) is that vector padded with
+// zeros.
+template <class B>
+struct CubeForm {
+  using L = typename B::Lat;
+  static constexpr int Q = B::Q;
+  struct Mask {
+    bool m[27] = {};
   };
-  sfor<3>([&](auto i) { sfor<3>([&](auto j) { pass(c[i][j][0], c[i][j][1], c[i][j][2]); }); });
-  sfor<3>([&](auto i) { sfor<3>([&](auto k) { pass(c[i][0][k], c[i][1][k], c[i][2][k]); }); });
-  sfor<3>([&](auto j) { sfor<3>([&](auto k) { pass(c[0][j][k], c[1][j][k], c[2][j][k]); }); });
-  sfor<27>([&](auto kk) {
-    constexpr int K = kk;
-    m[K] = c[kExp27[K][0]][kExp27[K][1]][kExp27[K][2]];
+  static constexpr int node(int c) { return c == 0 ? 0 : (c > 0 ? 1 : 2); }
+  static constexpr int cell(int a, int b, int e) { return (a * 3 + b) * 3 + e; }
+  static constexpr int pop_cell(int j) { return cell(node(L::c[j].x), node(L::c[j].y), node(L::c[j].z)); }
+  static constexpr int mom_cell(int k) {
+    const Poly p = B::W(k);
+    return cell(p.t[0].a, p.t[0].b, p.t[0].e);
+  }
+  static constexpr int ipow(int c, int n) { return n == 0 ? 1 : c * ipow(c, n - 1); }
+  static constexpr bool applies() {
+    for (int j = 0; j < Q; ++j) {
+      const int c[3] = {L::c[j].x, L::c[j].y, L::c[j].z};
+      for (int ax = 0; ax < 3; ++ax)
+        if (c[ax] < -1 || c[ax] > 1) return false;
+    }
+    bool used[27] = {};
+    for (int k = 0; k < Q; ++k) {
+      const Poly p = B::W(k);
+      if (p.n != 1 || !(p.t[0].c == Rat(1)) || p.t[0].a > 2 || p.t[0].b > 2 || p.t[0].e > 2) return false;
+      if (used[mom_cell(k)]) return false;
+      used[mom_cell(k)] = true;
+    }
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b)
+        for (int e = 0; e < 3; ++e)
+          if (!used[cell(a, b, e)])
+            for (int j = 0; j < Q; ++j)
+              if (ipow(L::c[j].x, a) * ipow(L::c[j].y, b) * ipow(L::c[j].z, e) != 0) return false;
+    return true;
+  }
+  static constexpr int stride(int ax) { return ax == 0 ? 9 : (ax == 1 ? 3 : 1); }
+  // first cell of line i (0..8) along axis ax
+  static constexpr int line(int ax, int i) {
+    const int u = i / 3, v = i % 3;
+    return ax == 0 ? cell(0, u, v) : (ax == 1 ? cell(u, 0, v) : cell(u, v, 0));
+  }
+  // cells holding a value before forward pass `stage` (passes along x, y, z)
+  static constexpr Mask fwd_mask(int stage) {
+    Mask m;
+    for (int j = 0; j < Q; ++j) m.m[pop_cell(j)] = true;
+    for (int ax = 0; ax < stage; ++ax)
+      for (int i = 0; i < 9; ++i) {
+        const int i0 = line(ax, i), i1 = i0 + stride(ax), i2 = i0 + 2 * stride(ax);
+        const bool A = m.m[i0], P = m.m[i1], M = m.m[i2];
+        m.m[i0] = A || P || M;
+        m.m[i1] = m.m[i2] = P || M;
+      }
+    return m;
+  }
+  // cells holding a value before inverse pass `stage` (passes along x, y, z),
+  // starting from the non-conserved moments k > d
+  static constexpr Mask inv_mask(int stage) {
+    Mask m;
+    for (int k = L::D + 1; k < Q; ++k) m.m[mom_cell(k)] = true;
+    for (int ax = 0; ax < stage; ++ax)
+      for (int i = 0; i < 9; ++i) {
+        const int i0 = line(ax, i), i1 = i0 + stride(ax), i2 = i0 + 2 * stride(ax);
+        const bool A = m.m[i0], P = m.m[i1], M = m.m[i2];
+        m.m[i0] = A || M;
+        m.m[i1] = m.m[i2] = P || M;
+      }
+    return m;
+  }
+};
+
+// m_k = sum_j W_k(c_j) h_j for every basis monomial (the conserved ones too).
+// One axis: (p0, p+, p-) -> (p0 + p+ + p-, p+ - p-, p+ + p-).
+template <class B, class T>
+__device__ __forceinline__ void cube_moments(const T (&h)[B::Q], T (&m)[B::Q]) {
+  using C = CubeForm<B>;
+  T c[27];
+  sfor<B::Q>([&](auto jj) { c[C::pop_cell(jj)] = h[jj]; });
+  sfor<3>([&](auto ax) {
+    constexpr int AX = ax;
+    constexpr typename C::Mask M = C::fwd_mask(AX);
+    sfor<9>([&](auto ii) {
+      constexpr int i0 = C::line(AX, ii), i1 = i0 + C::stride(AX), i2 = i0 + 2 * C::stride(AX);
+      constexpr bool A = M.m[i0], P = M.m[i1], N = M.m[i2];
+      if constexpr (P && N) {
+        const T sum = c[i1] + c[i2], dif = c[i1] - c[i2];
+        if constexpr (A) c[i0] = c[i0] + sum;
+        else c[i0] = sum;
+        c[i1] = dif;
+        c[i2] = sum;
+      } else if constexpr (P) {
+        if constexpr (A) c[i0] = c[i0] + c[i1];
+        else c[i0] = c[i1];
+        c[i2] = c[i1];
+      } else if constexpr (N) {
+        if constexpr (A) c[i0] = c[i0] + c[i2];
+        else c[i0] = c[i2];
+        c[i1] = -c[i2];
+      }
+    });
   });
+  sfor<B::Q>([&](auto kk) { m[kk] = c[C::mom_cell(kk)]; });
 }
 
-// 2^{|c_j|^2} (M_W(0)^{-1} m)_j.  One axis of the inverse is
+// dh_j = 2^{|c_j|^2} (M_W(0)^{-1} dm)_j for a moment change dm that vanishes on
+// the conserved moments.  One axis of the inverse is
 // (m0, m1, m2) -> (m0 - m2, (m1 + m2)/2, (m2 - m1)/2); the halves belong to
 // the population index, so the passes leave them out and the caller applies
 // 2^{-|c_j|^2} once per population.
-template <class T>
-__device__ __forceinline__ void t27_populations(const T (&m)[27], T (&dh)[27]) {
-  using L = D3Q27Lat;
-  T c[3][3][3];
-  sfor<27>([&](auto kk) {
-    constexpr int K = kk;
-    c[kExp27[K][0]][kExp27[K][1]][kExp27[K][2]] = m[K];
+template <class B, class T>
+__device__ __forceinline__ void cube_populations(const T (&dm)[B::Q], T (&dh)[B::Q]) {
+  using C = CubeForm<B>;
+  constexpr int D = B::Lat::D;
+  T c[27];
+  sfor<B::Q>([&](auto kk) {
+    if constexpr (kk > D) c[C::mom_cell(kk)] = dm[kk];
   });
-  auto pass = [](T& q0, T& q1, T& q2) {
-    const T f0 = q0 - q2, fp = q1 + q2, fm = q2 - q1;
-    q0 = f0;
-    q1 = fp;
-    q2 = fm;
-  };
-  sfor<3>([&](auto j) { sfor<3>([&](auto k) { pass(c[0][j][k], c[1][j][k], c[2][j][k]); }); });
-  sfor<3>([&](auto i) { sfor<3>([&](auto k) { pass(c[i][0][k], c[i][1][k], c[i][2][k]); }); });
-  sfor<3>([&](auto i) { sfor<3>([&](auto j) { pass(c[i][j][0], c[i][j][1], c[i][j][2]); }); });
-  sfor<27>([&](auto jj) {
-    constexpr int J = jj;
-    dh[J] = c[t27_axis_index(L::c[J].x)][t27_axis_index(L::c[J].y)][t27_axis_index(L::c[J].z)];
+  sfor<3>([&](auto ax) {
+    constexpr int AX = ax;
+    constexpr typename C::Mask M = C::inv_mask(AX);
+    sfor<9>([&](auto ii) {
+      constexpr int i0 = C::line(AX, ii), i1 = i0 + C::stride(AX), i2 = i0 + 2 * C::stride(AX);
+      constexpr bool A = M.m[i0], P = M.m[i1], N = M.m[i2];
+      if constexpr (N) {
+        const T q0 = c[i0], q1 = c[i1], q2 = c[i2];
+        if constexpr (A) c[i0] = q0 - q2;
+        else c[i0] = -q2;
+        if constexpr (P) {
+          c[i1] = q1 + q2;
+          c[i2] = q2 - q1;
+        } else {
+          c[i1] = q2;
+          c[i2] = q2;
+        }
+      } else if constexpr (P) {
+        c[i2] = -c[i1];
+      }
+    });
+  });
+  constexpr typename C::Mask F = C::inv_mask(3);
+  sfor<B::Q>([&](auto jj) {
+    if constexpr (F.m[C::pop_cell(jj)]) dh[jj] = c[C::pop_cell(jj)];
+    else dh[jj] = zsum<T>();
   });
 }
 
@@ -173,10 +274,13 @@ __device__ __forceinline__ void collide_node(T (&h)[B::Q], const StepArgs<T>& a,
   constexpr int D = L::D;
   using Tb = Tab<B>;
 
-  // D3Q27: all working-basis moments of h in three one-axis passes
-  constexpr bool tensor = std::is_same_v<B, BasisD3Q27>;
-  T mw[tensor ? 27 : 1];
-  if constexpr (tensor) t27_moments(h, mw);
+  // monomial bases on {0, +-1}^d velocities: all working-basis moments of h
+  // in three one-axis passes.  FP32 arithmetic only: with 8-byte values the
+  // cube's live cells raise the register count (D3Q19: 96 -> 132 VGPRs, two
+  // wavefronts per SIMD fewer), and the sparse rows measured 2.9 % faster.
+  constexpr bool tensor = CubeForm<B>::applies() && sizeof(T) == 4;
+  T mw[tensor ? Q : 1];
+  if constexpr (tensor) cube_moments<B>(h, mw);
 
   // conserved moments, eq. (rhoq): rho = rho0 + sum h, j = sum c h
   T drho, jm[3] = {zsum<T>(), zsum<T>(), zsum<T>()};
@@ -355,8 +459,8 @@ __device__ __forceinline__ void collide_node(T (&h)[B::Q], const StepArgs<T>& a,
 
   // back to populations: h += M_W(0)^{-1} dm  (dm vanishes on the conserved block)
   if constexpr (tensor) {
-    T dh[27];
-    t27_populations(dl, dh);
+    T dh[Q];
+    cube_populations<B>(dl, dh);
     sfor<Q>([&](auto jj) {
       constexpr int J = jj;
       constexpr int c2 = L::c[J].x * L::c[J].x + L::c[J].y * L::c[J].y + L::c[J].z * L::c[J].z;

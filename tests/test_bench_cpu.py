@@ -1,0 +1,66 @@
+"""Host-side checks of the benchmark script and of the committed profile
+summaries it quotes (no GPU needed)."""
+import glob
+import importlib.util
+import os
+import re
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _bench_module():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def _profile_for(workload, streaming):
+    hits = glob.glob(os.path.join(ROOT, "profiles", "k_step*_%s_%s.md" % (workload, streaming)))
+    assert len(hits) == 1, (workload, streaming, hits)
+    return open(hits[0]).read()
+
+
+def test_every_traffic_figure_is_the_one_its_profile_records():
+    """bench.py reports roofline.traffic from FETCH_SIZE/WRITE_SIZE counters;
+    each figure must match the summary committed under profiles/ for the same
+    workload (the fused kernel, or the mean of the two in-place kernels)."""
+    bench = _bench_module()
+    assert bench.TRAFFIC_GB
+    for (workload, streaming), gb in bench.TRAFFIC_GB.items():
+        assert workload in bench.WORKLOADS
+        text = _profile_for(workload, streaming)
+        rows = re.findall(r"^\| `k_step<[^`]*, (\d), \d>`[^|]*\| [\d,.]+ \| [\d,.]+ \| ([\d.]+) \| ([\d.]+) \|$",
+                          text, re.M)
+        assert rows, (workload, streaming)
+        if streaming == "aa":
+            vals = [float(t) for kind, t, _ in rows if kind in "456"]
+            assert len(vals) == 2
+            got = sum(vals) / 2
+        else:
+            kind = {"pull": "0", "push": "1"}[streaming]
+            vals = [float(t) for k, t, _ in rows if k == kind]
+            assert len(vals) == 1
+            got = vals[0]
+        assert abs(got - gb) <= 6e-5, (workload, streaming, got, gb)
+        # and the counters stay within 1.1 % of the algorithmic bytes
+        algo = float(rows[0][2])
+        assert abs(gb / algo - 1) < 0.011, (workload, streaming, gb, algo)
+
+
+def test_profile_commands_run_committed_files_only():
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
+        text = open(path).read()
+        assert "_work" not in text, path
+        for cmd in re.findall(r"^    (?:timeout -s KILL \d+ )?rocprofv3 .*$", text, re.M):
+            assert "-- " in cmd or cmd.endswith("\\"), (path, cmd)

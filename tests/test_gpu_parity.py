@@ -290,3 +290,24 @@ def test_lambda_scale_fp64():
     ctx = Lbmrv("d2q9", workloads.RATES_D2Q9_GROUPED, (23, 20), "f64", lam=lam)
     got = run_gpu(ctx, f0, 10, "field", field=field)
     assert rel(got, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("nsteps", [1, 7])
+def test_geier_basis_with_u_equals_appendix_b_cascaded_step(nsteps):
+    """Prop. th:cascd2q9 on the GPU: the Geier basis with u~ = u reproduces the
+    g-vector cascaded step of Appendix B (Oracle D, written separately from
+    Oracle A), far from equilibrium, over a ragged 70 x 13 grid."""
+    from oracle import geier
+    lat = oracle_lattice("d2q9", "geier")
+    shape = (13, 70)
+    f0 = far_state(lat, shape, seed=31, amp=0.05, umax=0.15)
+    s = [0, 0, 0, 1.1, 1.8, 1.6, 1.25, 1.35, 1.5]
+    ref = f0.copy()
+    for _ in range(nsteps):
+        ref = geier.geier_step(ref, s)
+    ctx = Lbmrv("d2q9", s, tuple(reversed(shape)), "f64", "geier")
+    got = run_gpu(ctx, f0, nsteps, "fluid", 1.0)
+    assert rel(got, ref) <= 1e-12
+    # the same state under the fixed-frame (MRT) relaxation is far from it
+    mrt = run_gpu(ctx, f0, nsteps, "zero")
+    assert rel(mrt, ref) > 1e-5

@@ -278,13 +278,13 @@ __device__ __forceinline__ void collide_node(T (&h)[B::Q], const StepArgs<T>& a,
   // in three one-axis passes.  FP32 arithmetic only: with 8-byte values the
   // cube's live cells raise the register count (D3Q19: 96 -> 132 VGPRs, two
   // wavefronts per SIMD fewer), and the sparse rows measured 2.9 % faster.
-  constexpr bool tensor = CubeForm<B>::applies() && sizeof(T) == 4;
-  T mw[tensor ? Q : 1];
-  if constexpr (tensor) cube_moments<B>(h, mw);
+  constexpr bool cube = CubeForm<B>::applies() && sizeof(T) == 4;
+  T mw[cube ? Q : 1];
+  if constexpr (cube) cube_moments<B>(h, mw);
 
   // conserved moments, eq. (rhoq): rho = rho0 + sum h, j = sum c h
   T drho, jm[3] = {zsum<T>(), zsum<T>(), zsum<T>()};
-  if constexpr (tensor) {
+  if constexpr (cube) {
     drho = mw[0];
     sfor<3>([&](auto al) { jm[al] = mw[1 + al]; });
   } else {
@@ -324,7 +324,7 @@ __device__ __forceinline__ void collide_node(T (&h)[B::Q], const StepArgs<T>& a,
     constexpr int K = kk;
     if constexpr (K <= D) {
       dl[K] = zsum<T>();
-    } else if constexpr (tensor) {
+    } else if constexpr (cube) {
       mh[K] = mw[K];
     } else {
       mh[K] = zsum<T>();
@@ -458,7 +458,7 @@ __device__ __forceinline__ void collide_node(T (&h)[B::Q], const StepArgs<T>& a,
   if constexpr (MODE != UT_ZERO) shift(T(1));
 
   // back to populations: h += M_W(0)^{-1} dm  (dm vanishes on the conserved block)
-  if constexpr (tensor) {
+  if constexpr (cube) {
     T dh[Q];
     cube_populations<B>(dl, dh);
     sfor<Q>([&](auto jj) {

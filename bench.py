@@ -195,6 +195,37 @@ def adjoint_costs(torch):
     return out
 
 
+def side_kernels(ctx, f, b, torch, reps=20):
+    """The moments output (rho, u; and with all q moments m(0)) and the FP64
+    conservation reduction on the benchmark state: time per call and the
+    algorithmic bytes moved per second.  The reduction returns host values,
+    so its figure is wall time per call, synchronisation included."""
+    N, q, d = ctx.N, ctx.q, ctx.d
+    bo = 8 if b == 8 else 4
+    stream = torch.cuda.current_stream()
+    res = {}
+    for key, with_m0 in (("moments", False), ("moments_m0", True)):
+        ctx.moments(f, with_m0)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            ctx.moments(f, with_m0)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        nbytes = q * b * N + (1 + d + (q if with_m0 else 0)) * bo * N
+        res[key] = {"us": round(us, 1), "GB_s": round(nbytes / (us * 1e-6) / 1e9, 1)}
+    ctx.conservation(f)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.conservation(f)
+    us = (time.perf_counter() - t0) * 1e6 / reps
+    res["conservation"] = {"us_wall": round(us, 1), "GB_s_wall": round(q * b * N / (us * 1e-6) / 1e9, 1)}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -288,6 +319,7 @@ def main():
         "state_finite": bool(finite),
         "wall_s": round(wall, 4),
     }
+    out["side_kernels"] = side_kernels(ctx, f, b, torch)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_costs(torch)
     if not args.no_cpu_baseline:

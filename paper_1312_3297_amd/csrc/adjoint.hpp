@@ -77,19 +77,29 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
     else g[J] = *src;
   });
 
-  // ---- forward quantities at this node
-  T drho = h[0];
-  sfor<Q - 1>([&](auto jj) { drho += h[jj + 1]; });
-  T jm[3] = {zsum<T>(), zsum<T>(), zsum<T>()};
-  sfor<Q>([&](auto jj) {
-    constexpr int J = jj;
-    if constexpr (L::c[J].x > 0) jm[0] += h[J];
-    if constexpr (L::c[J].x < 0) jm[0] -= h[J];
-    if constexpr (L::c[J].y > 0) jm[1] += h[J];
-    if constexpr (L::c[J].y < 0) jm[1] -= h[J];
-    if constexpr (L::c[J].z > 0) jm[2] += h[J];
-    if constexpr (L::c[J].z < 0) jm[2] -= h[J];
-  });
+  // ---- forward quantities at this node (monomial bases on {0, +-1}^d with
+  // FP32 arithmetic: all moments, and below the two transposed maps, by the
+  // cube passes of the forward kernel)
+  constexpr bool cube = CubeForm<B>::applies() && sizeof(T) == 4;
+  T mw[cube ? Q : 1];
+  if constexpr (cube) cube_moments<B>(h, mw);
+  T drho, jm[3] = {zsum<T>(), zsum<T>(), zsum<T>()};
+  if constexpr (cube) {
+    drho = mw[0];
+    sfor<D>([&](auto al) { jm[al] = mw[1 + al]; });
+  } else {
+    drho = h[0];
+    sfor<Q - 1>([&](auto jj) { drho += h[jj + 1]; });
+    sfor<Q>([&](auto jj) {
+      constexpr int J = jj;
+      if constexpr (L::c[J].x > 0) jm[0] += h[J];
+      if constexpr (L::c[J].x < 0) jm[0] -= h[J];
+      if constexpr (L::c[J].y > 0) jm[1] += h[J];
+      if constexpr (L::c[J].y < 0) jm[1] -= h[J];
+      if constexpr (L::c[J].z > 0) jm[2] += h[J];
+      if constexpr (L::c[J].z < 0) jm[2] -= h[J];
+    });
+  }
   const T rho = a.rho0 + drho;
   const T irho = T(1) / rho;
   const T u[3] = {jm[0] * irho, jm[1] * irho, D == 3 ? jm[2] * irho : T(0)};
@@ -151,6 +161,8 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
     constexpr int K = kk;
     if constexpr (K <= D) {
       v[K] = zsum<T>();
+    } else if constexpr (cube) {
+      mh[K] = mw[K];
     } else {
       mh[K] = zsum<T>();
       sfor<Tb::t.sMW[K].n>([&](auto i) { axpy_c<Tb::t.sMW[K].val[i]>(mh[K], h[Tb::t.sMW[K].col[i]]); });
@@ -266,14 +278,18 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
   }
 
   // ---- adjoint
-  T zz[Q];  // z1 -> z2 (in place through the shift)
-  sfor<Q>([&](auto kk) {
-    constexpr int K = kk;
-    T acc = zsum<T>();
-    if constexpr (K > D)
-      sfor<Tb::t.tMWinv[K].n>([&](auto i) { axpy_c<Tb::t.tMWinv[K].val[i]>(acc, g[Tb::t.tMWinv[K].col[i]]); });
-    zz[K] = acc;
-  });
+  T zz[Q];  // z1 = M_W(0)^{-T} g, then z2 (in place through the shift)
+  if constexpr (cube) {
+    cube_populations_t<B>(g, zz);
+  } else {
+    sfor<Q>([&](auto kk) {
+      constexpr int K = kk;
+      T acc = zsum<T>();
+      if constexpr (K > D)
+        sfor<Tb::t.tMWinv[K].n>([&](auto i) { axpy_c<Tb::t.tMWinv[K].val[i]>(acc, g[Tb::t.tMWinv[K].col[i]]); });
+      zz[K] = acc;
+    });
+  }
   if constexpr (MODE != UT_ZERO) apply_shift(zz, T(1), std::true_type{});  // z2 = T(-u~)^T z1
 
   T z3[Q], z5[Q];  // z3 = R^{-T} z2, z5 = R^T S z3
@@ -373,10 +389,16 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
   }
   if (active) {
     T* lo = a.lam_out;
+    T yt[cube ? Q : 1];  // M_W(0)^T z6
+    if constexpr (cube) cube_moments_t<B>(z5, yt);
     sfor<Q>([&](auto jj) {
       constexpr int J = jj;
       T yv = zsum<T>();
-      sfor<Tb::t.tMW[J].n>([&](auto i) { axpy_c<Tb::t.tMW[J].val[i]>(yv, z5[Tb::t.tMW[J].col[i]]); });
+      if constexpr (cube) {
+        yv = yt[J];
+      } else {
+        sfor<Tb::t.tMW[J].n>([&](auto i) { axpy_c<Tb::t.tMW[J].val[i]>(yv, z5[Tb::t.tMW[J].col[i]]); });
+      }
       T lam = g[J] - yv + A0;
       sfor<D>([&](auto al) {
         constexpr int cj = al == 0 ? L::c[J].x : al == 1 ? L::c[J].y : L::c[J].z;

@@ -152,30 +152,38 @@ struct CubeForm {
     const int u = i / 3, v = i % 3;
     return ax == 0 ? cell(0, u, v) : (ax == 1 ? cell(u, 0, v) : cell(u, v, 0));
   }
-  // cells holding a value before forward pass `stage` (passes along x, y, z)
-  static constexpr Mask fwd_mask(int stage) {
+  // Which cells hold a value (all others are known zeros) before pass `stage`
+  // (passes along x, y, z) of one of the four maps, by the rule each map's
+  // one-axis step follows on a line of cells (p0, p+, p-) or (m0, m1, m2):
+  //   kFwd  M_W(0):        (a|p|n, p|n, p|n)   from the populations
+  //   kInv  its inverse:   (a|n,   p|n, p|n)   from the non-conserved moments
+  //   kFwdT M_W(0)^T:      (a, a|p|n, a|p|n)   from the non-conserved moments
+  //   kInvT its inverse^T: (a, p|n,   a|p|n)   from the populations
+  enum { kFwd = 0, kInv = 1, kFwdT = 2, kInvT = 3 };
+  static constexpr Mask mask(int map, int stage) {
     Mask m;
-    for (int j = 0; j < Q; ++j) m.m[pop_cell(j)] = true;
+    if (map == kFwd || map == kInvT) {
+      for (int j = 0; j < Q; ++j) m.m[pop_cell(j)] = true;
+    } else {
+      for (int k = L::D + 1; k < Q; ++k) m.m[mom_cell(k)] = true;
+    }
     for (int ax = 0; ax < stage; ++ax)
       for (int i = 0; i < 9; ++i) {
         const int i0 = line(ax, i), i1 = i0 + stride(ax), i2 = i0 + 2 * stride(ax);
-        const bool A = m.m[i0], P = m.m[i1], M = m.m[i2];
-        m.m[i0] = A || P || M;
-        m.m[i1] = m.m[i2] = P || M;
-      }
-    return m;
-  }
-  // cells holding a value before inverse pass `stage` (passes along x, y, z),
-  // starting from the non-conserved moments k > d
-  static constexpr Mask inv_mask(int stage) {
-    Mask m;
-    for (int k = L::D + 1; k < Q; ++k) m.m[mom_cell(k)] = true;
-    for (int ax = 0; ax < stage; ++ax)
-      for (int i = 0; i < 9; ++i) {
-        const int i0 = line(ax, i), i1 = i0 + stride(ax), i2 = i0 + 2 * stride(ax);
-        const bool A = m.m[i0], P = m.m[i1], M = m.m[i2];
-        m.m[i0] = A || M;
-        m.m[i1] = m.m[i2] = P || M;
+        const bool A = m.m[i0], P = m.m[i1], N = m.m[i2];
+        const bool any = A || P || N;
+        if (map == kFwd) {
+          m.m[i0] = any;
+          m.m[i1] = m.m[i2] = P || N;
+        } else if (map == kInv) {
+          m.m[i0] = A || N;
+          m.m[i1] = m.m[i2] = P || N;
+        } else if (map == kFwdT) {
+          m.m[i1] = m.m[i2] = any;
+        } else {
+          m.m[i1] = P || N;
+          m.m[i2] = any;
+        }
       }
     return m;
   }
@@ -190,7 +198,7 @@ __device__ __forceinline__ void cube_moments(const T (&h)[B::Q], T (&m)[B::Q]) {
   sfor<B::Q>([&](auto jj) { c[C::pop_cell(jj)] = h[jj]; });
   sfor<3>([&](auto ax) {
     constexpr int AX = ax;
-    constexpr typename C::Mask M = C::fwd_mask(AX);
+    constexpr typename C::Mask M = C::mask(C::kFwd, AX);
     sfor<9>([&](auto ii) {
       constexpr int i0 = C::line(AX, ii), i1 = i0 + C::stride(AX), i2 = i0 + 2 * C::stride(AX);
       constexpr bool A = M.m[i0], P = M.m[i1], N = M.m[i2];
@@ -229,7 +237,7 @@ __device__ __forceinline__ void cube_populations(const T (&dm)[B::Q], T (&dh)[B:
   });
   sfor<3>([&](auto ax) {
     constexpr int AX = ax;
-    constexpr typename C::Mask M = C::inv_mask(AX);
+    constexpr typename C::Mask M = C::mask(C::kInv, AX);
     sfor<9>([&](auto ii) {
       constexpr int i0 = C::line(AX, ii), i1 = i0 + C::stride(AX), i2 = i0 + 2 * C::stride(AX);
       constexpr bool A = M.m[i0], P = M.m[i1], N = M.m[i2];
@@ -249,10 +257,102 @@ __device__ __forceinline__ void cube_populations(const T (&dm)[B::Q], T (&dh)[B:
       }
     });
   });
-  constexpr typename C::Mask F = C::inv_mask(3);
+  constexpr typename C::Mask F = C::mask(C::kInv, 3);
   sfor<B::Q>([&](auto jj) {
     if constexpr (F.m[C::pop_cell(jj)]) dh[jj] = c[C::pop_cell(jj)];
     else dh[jj] = zsum<T>();
+  });
+}
+
+// Transposes, for the adjoint.  M_W(0)^T z (moments -> populations), for z
+// that vanishes on the conserved moments; one axis is
+// (z0, z1, z2) -> (z0, z0 + z1 + z2, z0 - z1 + z2).  Exact for a lattice
+// smaller than the cube: the basis moments it lacks enter as zeros.
+template <class B, class T>
+__device__ __forceinline__ void cube_moments_t(const T (&z)[B::Q], T (&y)[B::Q]) {
+  using C = CubeForm<B>;
+  constexpr int D = B::Lat::D;
+  T c[27];
+  sfor<B::Q>([&](auto kk) {
+    if constexpr (kk > D) c[C::mom_cell(kk)] = z[kk];
+  });
+  sfor<3>([&](auto ax) {
+    constexpr int AX = ax;
+    constexpr typename C::Mask M = C::mask(C::kFwdT, AX);
+    sfor<9>([&](auto ii) {
+      constexpr int i0 = C::line(AX, ii), i1 = i0 + C::stride(AX), i2 = i0 + 2 * C::stride(AX);
+      constexpr bool A = M.m[i0], P = M.m[i1], N = M.m[i2];
+      if constexpr (A || P || N) {
+        T sum;  // z0 + z2
+        if constexpr (A && N) sum = c[i0] + c[i2];
+        else if constexpr (A) sum = c[i0];
+        else if constexpr (N) sum = c[i2];
+        if constexpr ((A || N) && P) {
+          c[i2] = sum - c[i1];
+          c[i1] = sum + c[i1];
+        } else if constexpr (A || N) {
+          c[i1] = sum;
+          c[i2] = sum;
+        } else {
+          c[i2] = -c[i1];
+        }
+      }
+    });
+  });
+  constexpr typename C::Mask F = C::mask(C::kFwdT, 3);
+  sfor<B::Q>([&](auto jj) {
+    if constexpr (F.m[C::pop_cell(jj)]) y[jj] = c[C::pop_cell(jj)];
+    else y[jj] = zsum<T>();
+  });
+}
+
+// M_W(0)^{-T} g on the non-conserved moments (populations -> moments): the
+// populations are first scaled by 2^{-|c_j|^2} (the inverse's halves), then
+// one axis is (p0, p+, p-) -> (p0, p+ - p-, p+ + p- - p0).  The conserved
+// entries (k <= d) are set to -0.
+template <class B, class T>
+__device__ __forceinline__ void cube_populations_t(const T (&g)[B::Q], T (&zm)[B::Q]) {
+  using C = CubeForm<B>;
+  using L = typename B::Lat;
+  constexpr int D = L::D;
+  T c[27];
+  sfor<B::Q>([&](auto jj) {
+    constexpr int J = jj;
+    constexpr int c2 = L::c[J].x * L::c[J].x + L::c[J].y * L::c[J].y + L::c[J].z * L::c[J].z;
+    if constexpr (c2 == 0) c[C::pop_cell(J)] = g[J];
+    else c[C::pop_cell(J)] = T(1.0 / (1 << c2)) * g[J];
+  });
+  sfor<3>([&](auto ax) {
+    constexpr int AX = ax;
+    constexpr typename C::Mask M = C::mask(C::kInvT, AX);
+    sfor<9>([&](auto ii) {
+      constexpr int i0 = C::line(AX, ii), i1 = i0 + C::stride(AX), i2 = i0 + 2 * C::stride(AX);
+      constexpr bool A = M.m[i0], P = M.m[i1], N = M.m[i2];
+      if constexpr (P || N) {
+        T sum, dif;
+        if constexpr (P && N) {
+          sum = c[i1] + c[i2];
+          dif = c[i1] - c[i2];
+        } else if constexpr (P) {
+          sum = c[i1];
+          dif = c[i1];
+        } else {
+          sum = c[i2];
+          dif = -c[i2];
+        }
+        c[i1] = dif;
+        if constexpr (A) c[i2] = sum - c[i0];
+        else c[i2] = sum;
+      } else if constexpr (A) {
+        c[i2] = -c[i0];
+      }
+    });
+  });
+  constexpr typename C::Mask F = C::mask(C::kInvT, 3);
+  sfor<B::Q>([&](auto kk) {
+    constexpr int K = kk;
+    if constexpr (K <= D || !F.m[C::mom_cell(K)]) zm[K] = zsum<T>();
+    else zm[K] = c[C::mom_cell(K)];
   });
 }
 

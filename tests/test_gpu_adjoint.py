@@ -170,35 +170,44 @@ def test_adjoint_with_maxwellian_equilibria_fp64(lattice, basis, mode):
         assert rel(gug.cpu().numpy(), gu) <= 1e-10
 
 
-@pytest.mark.parametrize("lattice", ["d3q19", "d3q27"])
+@pytest.mark.parametrize("lattice,basis,eq", [("d3q19", "default", "polynomial"), ("d3q27", "default", "polynomial"),
+                                               ("d2q9", "geier", "polynomial"), ("d3q19", "default", "maxwellian")])
 @pytest.mark.parametrize("storage", ["f32", "f16dev"])
 @pytest.mark.parametrize("mode", ["field", "fluid"])
-def test_adjoint_3d_reduced_precision_storage(lattice, storage, mode):
-    """The FP32 and FP16-deviation 3-D adjoints (the instances with FP32
-    arithmetic) against Oracle E evaluated in FP64 from the same rounded
-    initial state.  Gates: FP32 as for D2Q9 (1e-4).  FP16: the GPU's forward
-    states stay within the parity gate 8e-5 (n + 1) ||f|| of the FP64 ones
-    (5.6e-4 at n = 6), and the adjoint's coefficients (rho, u, the shifted
-    moments) depend smoothly on them near equilibrium, so the gradients are
-    gated at 5e-3, about ten times that state bound."""
-    lat = oracle_lattice(lattice)
-    shape = (4, 5, 6)
+def test_adjoint_reduced_precision_storage(lattice, basis, eq, storage, mode):
+    """The FP32 and FP16-deviation adjoints of the monomial bases (the
+    instances with FP32 arithmetic, which apply M_W(0), its inverse and their
+    transposes as one-axis passes) against Oracle E evaluated in FP64 from the
+    same rounded initial state.  Gates: FP32 as for the D2Q9 paper basis
+    (1e-4).  FP16: the GPU's forward states stay within the parity gate
+    8e-5 (n + 1) ||f|| of the FP64 ones (5.6e-4 at n = 6), and the adjoint's
+    coefficients (rho, u, the shifted moments) depend smoothly on them near
+    equilibrium, so the gradients are gated at 5e-3, about ten times that
+    state bound."""
+    lat = oracle_lattice(lattice, basis)
     rng = np.random.default_rng(9)
-    rho, u = workloads.taylor_green(6, 0.05, shape=shape)
+    if lat.d == 3:
+        shape = (4, 5, 6)
+        rho, u = workloads.taylor_green(6, 0.05, shape=shape)
+    else:
+        shape = (12, 13)
+        rho = 1 + 0.01 * rng.standard_normal(shape)
+        u = 0.05 * rng.uniform(-1, 1, (2,) + shape)
     f0 = A.equilibrium(lat, rho, u) * (1 + 0.01 * rng.uniform(-1, 1, (lat.q,) + shape))
     st, f0w = to_storage(lat, f0, storage)
-    s = workloads.RATES_D3Q19 if lattice == "d3q19" else workloads.RATES_D3Q27
+    s = {9: workloads.RATES_D2Q9_GROUPED, 19: workloads.RATES_D3Q19, 27: workloads.RATES_D3Q27}[lat.q]
     n, K, alpha = 6, 3, 0.8
-    field = (0.1 * rng.uniform(-1, 1, (3,) + shape)).astype(np.float32).astype(np.float64)
+    field = (0.1 * rng.uniform(-1, 1, (lat.d,) + shape)).astype(np.float32).astype(np.float64)
     if mode == "field":
-        fN = A.run(lat, f0w, s, n, mode=A.FIELD, field=field)
+        fN = A.run(lat, f0w, s, n, mode=A.FIELD, field=field, eq=eq)
         _, cot = E.kinetic_energy(lat, fN)
-        _, gf, gs, gu = E.vjp(lat, f0w, s, n, cot, field=field, K=K)
+        _, gf, gs, gu = E.vjp(lat, f0w, s, n, cot, field=field, K=K, eq=eq)
     else:
-        fN = A.run(lat, f0w, s, n, mode=A.FLUID, alpha=alpha)
+        fN = A.run(lat, f0w, s, n, mode=A.FLUID, alpha=alpha, eq=eq)
         _, cot = E.kinetic_energy(lat, fN)
-        _, gf, gs, gu = E.vjp(lat, f0w, s, n, cot, alpha=alpha, K=K)
-    ctx = Lbmrv(lattice, s, tuple(reversed(shape)), storage)
+        _, gf, gs, gu = E.vjp(lat, f0w, s, n, cot, alpha=alpha, K=K, eq=eq)
+    ctx = Lbmrv(lattice, s, tuple(reversed(shape)), storage, basis)
+    ctx.set_equilibrium(eq)
     fld = gpu(field.astype(np.float32)) if mode == "field" else None
     _, gfg, gsg, gug = ctx.adjoint(gpu(st), gpu(cot, torch.float32), n, K, mode, fld, alpha=alpha)
     torch.cuda.synchronize()
@@ -206,5 +215,5 @@ def test_adjoint_3d_reduced_precision_storage(lattice, storage, mode):
     errs = [rel(gfg.cpu().numpy(), gf), rel(gsg.cpu().numpy(), gs)]
     if mode == "field":
         errs.append(rel(gug.cpu().numpy(), gu))
-    print(lattice, storage, mode, "relative errors", errs)
+    print(lattice, basis, eq, storage, mode, "relative errors", errs)
     assert max(errs) <= tol

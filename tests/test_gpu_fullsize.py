@@ -52,7 +52,7 @@ def _check(lattice, shape, storage, mode, streaming, rates, rho, u, noise_amp, s
     ctx = Lbmrv(lattice, rates, tuple(reversed(shape)), storage)
     ctx.set_streaming(streaming)
     fin = torch.from_numpy(st).to("cuda")
-    fout = torch.empty_like(fin)
+    fout = fin if streaming == "aa" else torch.empty_like(fin)   # the in-place form runs on one array
     fld = None if field is None else torch.from_numpy(field.astype(np.float32)).to("cuda")
     ctx.step(fin, fout, mode, 1.0, fld, NSTEPS)
     torch.cuda.synchronize()
@@ -79,23 +79,29 @@ def _check(lattice, shape, storage, mode, streaming, rates, rho, u, noise_amp, s
     assert rel(gv, ref) <= tol
 
 
-@pytest.mark.parametrize("streaming", ["push", "pull"])
+# every benchmark workload in the pull form it times (two-row blocks for D3Q27
+# FP32, one-row blocks and 5 wavefronts per SIMD for D3Q27 FP16, per-XCD block
+# order for D2Q9 2048^2), and the push and in-place forms of the headline
+@pytest.mark.parametrize("streaming", ["pull", "push", "aa"])
 def test_d3q19_taylor_green_256_f32_fluid(streaming):
     rho, u = workloads.taylor_green(256, 0.05)
     _check("d3q19", (256, 256, 256), "f32", "fluid", streaming, workloads.RATES_D3Q19, rho, u, 1e-5, 1313)
 
 
-def test_d3q19_taylor_green_256_f16dev_fluid():
+@pytest.mark.parametrize("storage", ["f16dev", "f64"])
+def test_d3q19_taylor_green_256_other_storages_fluid(storage):
     rho, u = workloads.taylor_green(256, 0.05)
-    _check("d3q19", (256, 256, 256), "f16dev", "fluid", "push", workloads.RATES_D3Q19, rho, u, 1e-5, 1313)
+    _check("d3q19", (256, 256, 256), storage, "fluid", "pull", workloads.RATES_D3Q19, rho, u, 1e-5, 1313)
 
 
-def test_d3q27_taylor_green_192_f32_field():
+@pytest.mark.parametrize("storage", ["f32", "f16dev"])
+def test_d3q27_taylor_green_192_field(storage):
     rho, u = workloads.taylor_green(192, 0.05)
-    _check("d3q27", (192, 192, 192), "f32", "field", "push", workloads.RATES_D3Q27, rho, u, 1e-5, 1314,
+    _check("d3q27", (192, 192, 192), storage, "field", "pull", workloads.RATES_D3Q27, rho, u, 1e-5, 1314,
            field=0.5 * u)
 
 
-def test_d2q9_double_shear_layer_2048_f32_fluid():
-    rho, u = workloads.double_shear_layer(2048)
-    _check("d2q9", (2048, 2048), "f32", "fluid", "push", workloads.RATES_D2Q9_SHEAR_LAYER, rho, u, 0.0, 7)
+@pytest.mark.parametrize("L", [2048, 4096])
+def test_d2q9_double_shear_layer_f32_fluid(L):
+    rho, u = workloads.double_shear_layer(L)
+    _check("d2q9", (L, L), "f32", "fluid", "pull", workloads.RATES_D2Q9_SHEAR_LAYER, rho, u, 0.0, 7)

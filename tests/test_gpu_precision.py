@@ -75,3 +75,40 @@ def test_taylor_green_64_precision(reference, storage, gate_rho, gate_u, gate_m)
     print("\nprecision %-7s after %d steps: rho %.3e (of rho-1: %.3e)  u %.3e  non-conserved moments %.3e"
           % (storage, NSTEPS, e_rho, e_rho1, e_u, e_m))
     assert e_rho <= gate_rho and e_u <= gate_u and e_m <= gate_m
+
+
+L27 = 32
+
+
+@pytest.fixture(scope="module")
+def reference_d3q27():
+    """D3Q27 Taylor-Green (U0 = 0.05, wavenumber 2 pi / 32, 1e-5 seeded noise)
+    with u~ = 0.5 u(x, 0) held as a field, the form of the D3Q27 workload."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    lat = oracle_lattice("d3q27")
+    rho, u = workloads.taylor_green(L27, 0.05)
+    f0 = A.equilibrium(lat, rho, u) + 1e-5 * workloads.noise(27, (L27,) * 3, 1314)
+    field = (0.5 * u).astype(np.float32).astype(np.float64)
+    ref = fast.run(lat, f0, workloads.RATES_D3Q27, NSTEPS, mode=A.FIELD, field=field,
+                   threads=min(16, os.cpu_count() or 1))
+    return lat, f0, field, ref
+
+
+@pytest.mark.parametrize("storage,gate_rho,gate_u,gate_m", [
+    ("f64", 1e-9, 1e-9, 1e-9), ("f32", 1e-5, 2e-5, 5e-4), ("f16dev", 5e-3, 5e-3, 5e-2)])
+def test_d3q27_field_precision(reference_d3q27, storage, gate_rho, gate_u, gate_m):
+    """The same gates as the D3Q19 case: the storage roundings per step are the
+    same, and the moment sums have at most 27 terms instead of 19."""
+    lat, f0, field, ref = reference_d3q27
+    st, _ = to_storage(lat, f0, storage)
+    ctx = Lbmrv("d3q27", workloads.RATES_D3Q27, (L27,) * 3, storage)
+    fin = torch.from_numpy(st).to("cuda")
+    fout = torch.empty_like(fin)
+    ctx.step(fin, fout, "field", 1.0, torch.from_numpy(field.astype(np.float32)).to("cuda"), NSTEPS)
+    torch.cuda.synchronize()
+    got = from_storage(lat, fout.cpu().numpy(), storage)
+    e_rho, e_rho1, e_u, e_m = field_errors(lat, got, ref)
+    print("\nD3Q27 field precision %-7s after %d steps: rho %.3e (of rho-1: %.3e)  u %.3e  "
+          "non-conserved moments %.3e" % (storage, NSTEPS, e_rho, e_rho1, e_u, e_m))
+    assert e_rho <= gate_rho and e_u <= gate_u and e_m <= gate_m

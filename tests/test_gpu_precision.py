@@ -96,7 +96,8 @@ def reference_d3q27():
 
 
 @pytest.mark.parametrize("storage,gate_rho,gate_u,gate_m", [
-    ("f64", 1e-9, 1e-9, 1e-9), ("f32", 1e-5, 2e-5, 5e-4), ("f16dev", 5e-3, 5e-3, 5e-2)])
+    ("f64", 1e-9, 1e-9, 1e-9), ("f32", 1e-5, 2e-5, 5e-4), ("f32dev", 1e-5, 1e-5, 2e-5),
+    ("f16dev", 5e-3, 5e-3, 5e-2)])
 def test_d3q27_field_precision(reference_d3q27, storage, gate_rho, gate_u, gate_m):
     """The same gates as the D3Q19 case: the storage roundings per step are the
     same, and the moment sums have at most 27 terms instead of 19."""

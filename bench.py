@@ -32,6 +32,7 @@ TRAFFIC_GB = {
     ("d3q19_tgv256_f32_fluid", "pull"): 2.5508,
     ("d3q19_tgv256_f16dev_fluid", "pull"): 1.2752,
     ("d3q19_tgv256_f64_fluid", "pull"): 5.1006,
+    ("d3q19_tgv256_f32dev_fluid", "pull"): 2.5508,
     ("d3q27_tgv192_f32_field", "pull"): 1.6595,
     ("d3q27_tgv192_f16dev_field", "pull"): 0.8731,
     ("d3q19_tgv256_f32_fluid", "aa"): 2.5504,
@@ -55,6 +56,7 @@ WORKLOADS = {
     # moving along x; Taylor-Green start as in the headline workload
     "d3q19_couette256_f32_fluid_walls": ("d3q19", (256, 256, 256), "f32", "fluid"),
     "d3q19_tgv256_f64_fluid": ("d3q19", (256, 256, 256), "f64", "fluid"),
+    "d3q19_tgv256_f32dev_fluid": ("d3q19", (256, 256, 256), "f32dev", "fluid"),
     "d3q27_tgv192_f16dev_field": ("d3q27", (192, 192, 192), "f16dev", "field"),
     # run-time moment basis (raw second moments, three normal-stress rates):
     # the relaxation goes through a dense R^{-1} S R instead of compiled tables

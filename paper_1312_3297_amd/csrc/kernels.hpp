@@ -219,7 +219,13 @@ __device__ __forceinline__ void cube_moments(const T (&h)[B::Q], T (&m)[B::Q]) {
       }
     });
   });
-  sfor<B::Q>([&](auto kk) { m[kk] = c[C::mom_cell(kk)]; });
+  constexpr typename C::Mask F = C::mask(C::kFwd, 3);
+  sfor<B::Q>([&](auto kk) {
+    // a basis monomial whose cell stayed empty would vanish on every velocity
+    // (and M_W(0) would be singular)
+    static_assert(F.m[C::mom_cell(kk)]);
+    m[kk] = c[C::mom_cell(kk)];
+  });
 }
 
 // dh_j = 2^{|c_j|^2} (M_W(0)^{-1} dm)_j for a moment change dm that vanishes on

@@ -101,7 +101,10 @@ typedef struct lbmrv_ctx lbmrv_ctx;
  *   s        q relaxation rates, one per basis element in the order above;
  *            s_k for the conserved moments (k = 0..d) must be exactly 0
  *            (section 1.1), the others in [0, 2]
- *   dims     d extents (nx, ny[, nz]), each >= 1, q*nx*ny*nz < 2^32
+ *   dims     d extents (nx, ny[, nz]), each >= 1, nx <= 65535*4096,
+ *            ny, nz <= 65535, and nx*ny*nz <= 2^32 - 256 nodes (node indices
+ *            are 32-bit; element offsets j*N + n are 64-bit, so q*N may
+ *            exceed 2^32)
  *   storage  enum lbmrv_storage
  *   rho0     reference density of the deviation storages (finite; ignored
  *            for LBMRV_F64 and LBMRV_F32)
@@ -215,17 +218,6 @@ int lbmrv_set_walls(lbmrv_ctx *c, uint32_t wall_mask, const double *wall_u, doub
  * Results are identical bit for bit in every order.  No HIP call.
  */
 int lbmrv_set_block_order(lbmrv_ctx *c, int order);
-
-/*
- * Replay of repeated step launches through HIP graphs (default off): the first
- * lbmrv_step call with a given pair of arrays, mode and parameters captures 16
- * consecutive passes into a graph on an internal stream (ordered after and
- * before hip_stream with events) and later calls replay it.  Results are
- * identical either way.  On MI355X direct launches already cost only ~4 us per
- * pass and graph replay measured slower for small grids, hence off by default.
- * No HIP call.
- */
-int lbmrv_set_graphs(lbmrv_ctx *c, int enable);
 
 /* Query: q, d, N (nodes), bytes per stored population. */
 int lbmrv_info(const lbmrv_ctx *c, int64_t *q, int64_t *d, int64_t *nodes, int64_t *bytes_per_pop);

@@ -16,7 +16,11 @@
 
 namespace lbmrv {
 
-__global__ __launch_bounds__(kRedThreads) void k_conserve_final(const double* partial, double* out) {
+// Totals of the kRedBlocks rows of five partial sums, in a fixed order:
+// out[0] = sum + add0, out[1 + a] = scale * sum (a < d, else 0), out[4] = the
+// count of non-finite values.
+__global__ __launch_bounds__(kRedThreads) void k_conserve_final(const double* partial, double* out, double add0,
+                                                                double scale, int d) {
   __shared__ double red[5][kRedThreads];
   double acc[5] = {0, 0, 0, 0, 0};
   for (int b = threadIdx.x; b < kRedBlocks; b += kRedThreads)
@@ -28,7 +32,9 @@ __global__ __launch_bounds__(kRedThreads) void k_conserve_final(const double* pa
       for (int i = 0; i < 5; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x < 5) out[threadIdx.x] = red[threadIdx.x][0];
+  if (threadIdx.x == 0) out[0] = red[0][0] + add0;
+  if (threadIdx.x >= 1 && threadIdx.x <= 3) out[threadIdx.x] = (int)threadIdx.x <= d ? scale * red[threadIdx.x][0] : 0.0;
+  if (threadIdx.x == 4) out[4] = red[4][0];
 }
 
 __global__ __launch_bounds__(256) void k_fill_zero(double* p, uint64_t n) {
@@ -125,23 +131,6 @@ struct lbmrv_ctx {
   double rho_w = 1.0;
   int equilibrium = LBMRV_EQ_POLYNOMIAL;
   int block_order = LBMRV_ORDER_AUTO;
-  // replay of repeated launches through HIP graphs (see run_alternating)
-  struct GraphEntry {
-    int kind_a, kind_b;
-    const void* p;
-    const void* q;
-    int mode;
-    double alpha;
-    const float* field;
-    uint64_t version;
-    hipGraphExec_t exec;
-  };
-  int graphs_on = 0;
-  int graph_dev = -1;
-  uint64_t version = 0;  // bumped whenever kernel arguments change
-  hipStream_t gstream = nullptr;
-  hipEvent_t gev[2] = {nullptr, nullptr};
-  std::vector<GraphEntry> graphs;
   // run-time basis P = R W (W the built-in working basis of `entry`)
   int custom = 0;
   std::vector<double> R;              // q x q
@@ -151,6 +140,8 @@ struct lbmrv_ctx {
 };
 
 namespace {
+
+constexpr uint64_t kMaxNodes = (1ull << 32) - 256;
 
 int lattice_q(int lattice) { return lattice == LBMRV_D2Q9 ? 9 : lattice == LBMRV_D3Q19 ? 19 : 27; }
 int lattice_d(int lattice) { return lattice == LBMRV_D2Q9 ? 2 : 3; }
@@ -223,72 +214,15 @@ hipError_t run_kind(const lbmrv_ctx* c, int kind, const void* fin, void* fout, i
 }
 
 // Launch count kernels alternating (kind_a: p -> q) and (kind_b: q -> p),
-// starting with the first; p == q for the in-place form.  With graphs on and
-// count >= kGraphChunk, a graph of kGraphChunk such launches is captured once
-// per (kinds, buffers, mode, alpha, field, argument version) on an internal
-// stream and replayed, which removes most of the per-launch host overhead of
-// small grids; the internal stream is ordered after and before the caller's
-// stream with events.
-constexpr int kGraphChunk = 16;
-
+// starting with the first; p == q for the in-place form.
 hipError_t run_alternating(lbmrv_ctx* c, int kind_a, int kind_b, void* p, void* q, int64_t count, int mode,
                            double alpha, const float* field, hipStream_t st) {
-  int dev = -1;
-  bool use = c->graphs_on && count >= kGraphChunk && hipGetDevice(&dev) == hipSuccess &&
-             (c->graph_dev < 0 || c->graph_dev == dev);
-  if (use && !c->gstream) {
-    if (hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&c->gev[0], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->gev[1], hipEventDisableTiming) != hipSuccess)
-      return hipErrorUnknown;
-    c->graph_dev = dev;
-  }
-  if (!use) {
-    for (int64_t i = 0; i < count; ++i) {
-      const bool even = i % 2 == 0;
-      hipError_t e = run_kind(c, even ? kind_a : kind_b, even ? p : q, even ? q : p, mode, alpha, field, st);
-      if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
-  }
-  hipGraphExec_t exec = nullptr;
-  for (auto& g : c->graphs)
-    if (g.kind_a == kind_a && g.kind_b == kind_b && g.p == p && g.q == q && g.mode == mode &&
-        g.alpha == alpha && g.field == field && g.version == c->version)
-      exec = g.exec;
-  hipError_t e;
-  if (!exec) {
-    if ((e = hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
-    hipError_t le = hipSuccess;
-    for (int i = 0; i < kGraphChunk && le == hipSuccess; ++i) {
-      const bool even = i % 2 == 0;
-      le = run_kind(c, even ? kind_a : kind_b, even ? p : q, even ? q : p, mode, alpha, field, c->gstream);
-    }
-    hipGraph_t graph = nullptr;
-    e = hipStreamEndCapture(c->gstream, &graph);
-    if (le != hipSuccess) e = le;
-    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (graph) (void)hipGraphDestroy(graph);
+  for (int64_t i = 0; i < count; ++i) {
+    const bool even = i % 2 == 0;
+    hipError_t e = run_kind(c, even ? kind_a : kind_b, even ? p : q, even ? q : p, mode, alpha, field, st);
     if (e != hipSuccess) return e;
-    if (c->graphs.size() >= 8) {  // keep a few entries
-      (void)hipGraphExecDestroy(c->graphs.front().exec);
-      c->graphs.erase(c->graphs.begin());
-    }
-    c->graphs.push_back({kind_a, kind_b, p, q, mode, alpha, field, c->version, exec});
   }
-  if ((e = hipEventRecord(c->gev[0], st)) != hipSuccess) return e;
-  if ((e = hipStreamWaitEvent(c->gstream, c->gev[0], 0)) != hipSuccess) return e;
-  const int64_t reps = count / kGraphChunk;
-  for (int64_t r = 0; r < reps; ++r)
-    if ((e = hipGraphLaunch(exec, c->gstream)) != hipSuccess) return e;
-  for (int64_t i = reps * kGraphChunk; i < count; ++i) {  // remainder starts with kind_a (chunk is even)
-    const bool even = (i - reps * kGraphChunk) % 2 == 0;
-    if ((e = run_kind(c, even ? kind_a : kind_b, even ? p : q, even ? q : p, mode, alpha, field, c->gstream)) !=
-        hipSuccess)
-      return e;
-  }
-  if ((e = hipEventRecord(c->gev[1], c->gstream)) != hipSuccess) return e;
-  return hipStreamWaitEvent(st, c->gev[1], 0);
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------- run-time bases
@@ -558,7 +492,10 @@ int lbmrv_create(lbmrv_ctx** out, int lattice, int basis, double lambda, const d
   }
   if (e[1] > 65535 || e[2] > 65535) return LBMRV_ERR_INVALID_ARG;  // grid y/z limits
   const uint64_t N = e[0] * e[1] * e[2];
-  if (N * (uint64_t)q >= (1ull << 32)) return LBMRV_ERR_INVALID_ARG;
+  // node indices are 32-bit (element offsets j * N + n are formed in 64 bits);
+  // the bound also keeps one-dimensional launches of 256-thread blocks below
+  // 2^32 work-items
+  if (N > kMaxNodes) return LBMRV_ERR_INVALID_ARG;
   lbmrv_ctx* c = new (std::nothrow) lbmrv_ctx();
   if (!c) return LBMRV_ERR_INVALID_ARG;
   c->lattice = lattice;
@@ -615,7 +552,6 @@ int lbmrv_set_rates(lbmrv_ctx* c, const double* s) {
   double old[27];
   for (int k = 0; k < 27; ++k) old[k] = c->s[k];
   for (int k = 0; k < c->q; ++k) c->s[k] = s[k];
-  ++c->version;
   if (c->custom && (rc = upload_basis(c))) {
     for (int k = 0; k < 27; ++k) c->s[k] = old[k];  // the context keeps its previous rates
     return rc;
@@ -633,7 +569,6 @@ int lbmrv_set_streaming(lbmrv_ctx* c, int kind) {
 int lbmrv_set_equilibrium(lbmrv_ctx* c, int kind) {
   if (!c || (kind != LBMRV_EQ_POLYNOMIAL && kind != LBMRV_EQ_MAXWELLIAN)) return LBMRV_ERR_INVALID_ARG;
   c->equilibrium = kind;
-  ++c->version;
   return LBMRV_OK;
 }
 
@@ -641,13 +576,6 @@ int lbmrv_set_block_order(lbmrv_ctx* c, int order) {
   if (!c || (order != LBMRV_ORDER_AUTO && order != LBMRV_ORDER_NATURAL && order != LBMRV_ORDER_XCD))
     return LBMRV_ERR_INVALID_ARG;
   c->block_order = order;
-  ++c->version;
-  return LBMRV_OK;
-}
-
-int lbmrv_set_graphs(lbmrv_ctx* c, int enable) {
-  if (!c) return LBMRV_ERR_INVALID_ARG;
-  c->graphs_on = enable ? 1 : 0;
   return LBMRV_OK;
 }
 
@@ -666,7 +594,6 @@ int lbmrv_set_walls(lbmrv_ctx* c, uint32_t wall_mask, const double* wall_u, doub
   for (int f = 0; f < 6; ++f)
     for (int ax = 0; ax < 3; ++ax) c->wall_u[f][ax] = u[f][ax];
   c->rho_w = rho_w;
-  ++c->version;
   return LBMRV_OK;
 }
 
@@ -809,9 +736,10 @@ int lbmrv_moments(lbmrv_ctx* c, const void* f, void* rho, void* u, void* m0, voi
 
 // Runs a partial-sum kernel over the context's reduction buffer (allocated on
 // the first call, on the current device), sums its kRedBlocks rows in a fixed
-// order and copies the five totals to the host; blocking on `st`.
+// order (the total of slot 0 plus add0, slots 1..d times scale) and copies the
+// five totals to the host; blocking on `st`.
 extern "C++" template <class Partial>
-static int reduce5(lbmrv_ctx* c, Partial partial, hipStream_t st, double (&h)[5]) {
+static int reduce5(lbmrv_ctx* c, Partial partial, double add0, double scale, hipStream_t st, double (&h)[5]) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return LBMRV_ERR_HIP;
   if (c->partial && c->partial_dev != dev) return LBMRV_ERR_INVALID_ARG;  // context bound to its first device
@@ -824,12 +752,16 @@ static int reduce5(lbmrv_ctx* c, Partial partial, hipStream_t st, double (&h)[5]
   }
   if (partial(c->partial) != hipSuccess) return LBMRV_ERR_HIP;
   double* res = c->partial + kRedBlocks * 5;
-  hipLaunchKernelGGL(k_conserve_final, dim3(1), dim3(kRedThreads), 0, st, c->partial, res);
+  hipLaunchKernelGGL(k_conserve_final, dim3(1), dim3(kRedThreads), 0, st, c->partial, res, add0, scale, c->d);
   if (hipGetLastError() != hipSuccess) return LBMRV_ERR_HIP;
   if (hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess) return LBMRV_ERR_HIP;
   if (hipStreamSynchronize(st) != hipSuccess) return LBMRV_ERR_HIP;
   return LBMRV_OK;
 }
+
+// Sums of the stored values; a deviation storage adds back rho0 * N (the
+// weights sum to 1 and sum w_j c_j = 0), and the momentum is in units of v_j.
+static double conserve_add0(const lbmrv_ctx* c) { return c->rho0 * (double)c->N; }
 
 int lbmrv_conservation(lbmrv_ctx* c, const void* f, double out[4], void* hip_stream) {
   if (!c || !out) return LBMRV_ERR_INVALID_ARG;
@@ -837,12 +769,10 @@ int lbmrv_conservation(lbmrv_ctx* c, const void* f, double out[4], void* hip_str
   if ((rc = check_ptr(f, elem_bytes(c->storage)))) return rc;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   double h[5];
-  if ((rc = reduce5(c, [&](double* p) { return kEntries[c->entry].cons[c->sk](f, c->N, p, st); }, st, h)))
+  if ((rc = reduce5(c, [&](double* p) { return kEntries[c->entry].cons[c->sk](f, c->N, p, st); }, conserve_add0(c),
+                    c->lambda, st, h)))
     return rc;
-  // sum of the stored values; deviation storage adds back rho0 * N (sum of w_j = 1,
-  // sum of w_j c_j = 0)
-  out[0] = h[0] + c->rho0 * (double)c->N;
-  for (int a = 0; a < 3; ++a) out[1 + a] = a < c->d ? c->lambda * h[1 + a] : 0.0;
+  for (int i = 0; i < 4; ++i) out[i] = h[i];
   return h[4] > 0 ? LBMRV_ERR_NONFINITE : LBMRV_OK;
 }
 
@@ -867,7 +797,8 @@ int lbmrv_deviation_norm(lbmrv_ctx* c, const void* f, const double* f_ref, doubl
   if ((rc = check_ptr(f, elem_bytes(c->storage))) || (rc = dev_ref(c, f_ref, r))) return rc;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   double h[5];
-  if ((rc = reduce5(c, [&](double* p) { return kEntries[c->entry].dnorm[c->sk](f, c->N, r, p, st); }, st, h)))
+  if ((rc = reduce5(c, [&](double* p) { return kEntries[c->entry].dnorm[c->sk](f, c->N, r, p, st); }, 0.0, 1.0,
+                    st, h)))
     return rc;
   out[0] = h[0];
   return h[4] > 0 ? LBMRV_ERR_NONFINITE : LBMRV_OK;
@@ -1064,10 +995,6 @@ int lbmrv_adjoint(lbmrv_ctx* c, const void* f0, int ut_mode, double ut_alpha, co
 
 void lbmrv_destroy(lbmrv_ctx* c) {
   if (!c) return;
-  for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
-  if (c->gstream) (void)hipStreamDestroy(c->gstream);
-  for (auto& ev : c->gev)
-    if (ev) (void)hipEventDestroy(ev);
   if (c->partial) (void)hipFree(c->partial);
   if (c->dtab) (void)hipFree(c->dtab);
   delete c;

@@ -1047,6 +1047,7 @@ __global__ __launch_bounds__(256) void k_dev_scale(void* fp, uint64_t N, DevRef 
 }
 
 // Sums kRedBlocks partials in a fixed order (one block), deterministic.
-__global__ __launch_bounds__(kRedThreads) void k_conserve_final(const double* partial, double* out);
+__global__ __launch_bounds__(kRedThreads) void k_conserve_final(const double* partial, double* out, double add0,
+                                                                double scale, int d);
 
 }  // namespace lbmrv

@@ -41,7 +41,6 @@ _SIGS = {
     "lbmrv_set_streaming": (_c_int, [_c_void_p, _c_int]),
     "lbmrv_set_walls": (_c_int, [_c_void_p, ctypes.c_uint32, ctypes.POINTER(_c_double), _c_double]),
     "lbmrv_set_equilibrium": (_c_int, [_c_void_p, _c_int]),
-    "lbmrv_set_graphs": (_c_int, [_c_void_p, _c_int]),
     "lbmrv_set_block_order": (_c_int, [_c_void_p, _c_int]),
     "lbmrv_info": (_c_int, [_c_void_p] + [ctypes.POINTER(_c_int64)] * 4),
     "lbmrv_step": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_int, _c_double, _c_void_p, _c_int64, _c_void_p]),
@@ -203,9 +202,6 @@ class Lbmrv:
 
     def set_block_order(self, order):
         _check(library().lbmrv_set_block_order(self._h, BLOCK_ORDERS[order]), "lbmrv_set_block_order")
-
-    def set_graphs(self, enable):
-        _check(library().lbmrv_set_graphs(self._h, 1 if enable else 0), "lbmrv_set_graphs")
 
     def set_equilibrium(self, kind):
         _check(library().lbmrv_set_equilibrium(self._h, EQUILIBRIA[kind]), "lbmrv_set_equilibrium")

@@ -68,8 +68,19 @@ def test_create_rejects_geier_basis_in_3d():
 
 
 def test_create_rejects_too_many_nodes():
+    # 2^32 nodes: node indices are 32-bit
     with pytest.raises(lbmrv.LbmrvError):
-        lbmrv.Lbmrv("d3q27", [0.0] * 4 + [1.0] * 23, (4096, 4096, 16))
+        lbmrv.Lbmrv("d2q9", GOOD9, (65536, 65536))
+    with pytest.raises(lbmrv.LbmrvError):
+        lbmrv.Lbmrv("d3q19", [0.0] * 4 + [1.0] * 15, (4096, 4096, 256))
+
+
+def test_create_accepts_more_than_2_32_elements():
+    # q * N >= 2^32 (element offsets are 64-bit); the largest N accepted is 2^32 - 256
+    lbmrv.Lbmrv("d3q27", [0.0] * 4 + [1.0] * 23, (4096, 4096, 16))
+    lbmrv.Lbmrv("d2q9", GOOD9, (65535 * 4096, 16))
+    with pytest.raises(lbmrv.LbmrvError):
+        lbmrv.Lbmrv("d2q9", GOOD9, (65535 * 4096, 17))
 
 
 class _Fake:

@@ -1,7 +1,8 @@
 """The largest and the smallest grids the interface accepts.
 
-Largest: q * nodes just below 2^32 (the limit lbmrv_create enforces), where
-element offsets pass 2^31.  The initial state is a periodic tiling of a small
+Largest: grids whose element offsets j * N + n pass 2^31 and 2^32 (q * N above
+2^32), up to the largest node count lbmrv_create accepts (2^32 - 256; node
+indices are 32-bit).  The initial state is a periodic tiling of a small
 block built on the host; a periodic start stays periodic under the scheme, so
 the oracle's run on the small periodic block is the exact answer at every node
 of the large grid, and sampled nodes (faces, corners, the last elements) are
@@ -35,7 +36,7 @@ def _tiled_case(lattice, block, reps, storage, mode, nsteps, tol, seed):
     q = lat.q
     dims_zyx = tuple(b * r for b, r in zip(block, reps))            # grid axes (z, y, x) or (y, x)
     nodes = int(np.prod(dims_zyx))
-    assert q * nodes < 2 ** 32
+    assert nodes <= 2 ** 32 - 256
     f0 = far_state(lat, block, seed=seed, amp=0.02, umax=0.08)
     st, f0w = to_storage(lat, f0, storage)
     ref = fast.run(lat, f0w, RATES[q], nsteps, mode={"zero": A.ZERO, "fluid": A.FLUID}[mode])
@@ -75,6 +76,17 @@ def _tiled_case(lattice, block, reps, storage, mode, nsteps, tol, seed):
 def test_largest_grid_d3q19_f16dev():
     # 215 x 1024 x 1024 nodes, q * N = 4,283,432,960 (2^32 - 11.5e6); 2 x 8.6 GB
     _tiled_case("d3q19", (43, 64, 64), (5, 16, 16), "f16dev", "fluid", 3, 5e-3, 71)
+
+
+def test_more_than_2_32_elements_d3q19_f16dev():
+    # 320 x 1024 x 1024 nodes, q * N = 6,375,342,080 (1.48 x 2^32); 2 x 12.7 GB
+    _tiled_case("d3q19", (32, 64, 64), (10, 16, 16), "f16dev", "fluid", 3, 5e-3, 75)
+
+
+def test_largest_node_count_d2q9_f16dev():
+    # 16 rows of 65535 * 4096 nodes: N = 4,294,901,760 = 2^32 - 65,536 (node
+    # offsets up to 2^32 - 65,537), q * N = 3.9e10; 2 x 77.3 GB
+    _tiled_case("d2q9", (4, 4096), (4, 65535), "f16dev", "fluid", 2, 5e-3, 76)
 
 
 def test_longest_row_d2q9_f32():

@@ -51,3 +51,22 @@ def rel(a, b):
     b = np.asarray(b, dtype=np.float64)
     den = np.abs(b).max()
     return float(np.abs(a - b).max() / (den if den > 0 else 1.0))
+
+
+def moment_bounds(lat, fw, lam, growth=8.0):
+    """Element-wise bounds for FP32 evaluations of rho, u and m(0) = M(0) f from
+    the stored state fw (widened to FP64): a sum of q products in FP32 errs by
+    at most about q 2^-24 times the sum of the magnitudes of its terms (the
+    deviation storages also add w_j rho0, with rho0 = 1, per term); `growth`
+    is the margin.  Returns the bounds for rho [grid], u [d, grid] and
+    m(0) [q, grid]."""
+    eps = growth * lat.q * 2.0 ** -24
+    M0 = np.abs(A.moment_matrix(lat, np.zeros((1, lat.d)), lam)[0])
+    mag = np.abs(fw) + lat.w.reshape((-1,) + (1,) * (fw.ndim - 1))
+    rho, u = A.conserved(lat, fw, lam)
+    t_rho = eps * mag.sum(axis=0)
+    v = np.abs(lat.velocities(lam))
+    t_u = np.stack([eps * (np.tensordot(v[:, a], mag, axes=(0, 0)) + np.abs(u[a]) * mag.sum(axis=0)) / rho
+                    for a in range(lat.d)])
+    t_m = eps * np.tensordot(M0, mag, axes=(1, 0))
+    return t_rho, t_u, t_m

@@ -15,7 +15,7 @@ from oracle import scheme as A
 from paper_1312_3297_amd import lbmrv, workloads as W
 from paper_1312_3297_amd.lbmrv import Lbmrv
 
-from _common import far_state, rel, to_storage
+from _common import far_state, moment_bounds, rel, to_storage
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -120,6 +120,27 @@ def test_custom_basis_moments(case):
     assert rel(m0.cpu().numpy(), ref) <= 1e-13
     r_rho, r_u = A.conserved(lat, f0)
     assert rel(rho.cpu().numpy(), r_rho) <= 1e-14 and rel(u.cpu().numpy(), r_u) <= 1e-13
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("storage", ["f32", "f32dev", "f16dev"])
+def test_custom_basis_moments_reduced_storage(case, storage):
+    """m(0) of a run-time basis in the FP32 storages: the kernel forms the
+    working-basis moments and applies R in FP32, so each moment errs by a few
+    ulp of the magnitudes it sums, amplified at most by the size of R's rows
+    (below 10 for these bases; growth 64 covers both)."""
+    lattice, polys, s, shape = CASES[case]
+    lat = lattices.with_basis(lattice, polys)
+    f0 = far_state(lat, shape, seed=36, amp=0.03, umax=0.1)
+    st, fw = to_storage(lat, f0, storage)
+    ctx = Lbmrv(lattice, s, tuple(reversed(shape)), storage, basis=polys)
+    rho, u, m0 = ctx.moments(torch.from_numpy(st).cuda(), with_m0=True)
+    torch.cuda.synchronize()
+    t_rho, t_u, t_m = moment_bounds(lat, fw, 1.0, growth=64.0)
+    r_rho, r_u = A.conserved(lat, fw)
+    assert np.all(np.abs(rho.cpu().numpy() - r_rho) <= t_rho)
+    assert np.all(np.abs(u.cpu().numpy() - r_u) <= t_u)
+    assert np.all(np.abs(m0.cpu().numpy() - A.fixed_moments(lat, fw)) <= t_m)
 
 
 def test_set_rates_on_a_runtime_basis_updates_the_table():

@@ -23,7 +23,7 @@ from oracle import scheme as A
 from paper_1312_3297_amd import workloads
 from paper_1312_3297_amd.lbmrv import Lbmrv
 
-from _common import far_state, from_storage, oracle_lattice, rel, to_storage
+from _common import far_state, from_storage, moment_bounds, oracle_lattice, rel, to_storage
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -213,6 +213,33 @@ def test_moments_fp64(lattice, basis, lam):
     assert rel(m0.cpu().numpy(), A.fixed_moments(lat, f0, lam)) <= 1e-14
 
 
+@pytest.mark.parametrize("lattice,basis", [("d2q9", "default"), ("d2q9", "geier"), ("d3q19", "default"),
+                                           ("d3q27", "default")])
+@pytest.mark.parametrize("storage", ["f32", "f32dev", "f16dev"])
+@pytest.mark.parametrize("lam", [1.0, 0.6])
+def test_moments_reduced_storage(lattice, basis, storage, lam):
+    """lbmrv_moments in the FP32 storages (FP32 arithmetic and output) against
+    eq. (rhoq) and m(0) = M(0) f (eq. (matort) for the D2Q9 paper basis) of the
+    widened stored state, element by element within the FP32 rounding bound;
+    the deviation storages add the rest moments of w_j rho0 back in."""
+    lat = oracle_lattice(lattice, basis)
+    shape = (10, 13) if lat.d == 2 else (3, 4, 5)
+    f0 = far_state(lat, shape, seed=5)
+    st, fw = to_storage(lat, f0, storage)
+    ctx = Lbmrv(lattice, np.zeros(lat.q), tuple(reversed(shape)), storage, basis, lam=lam)
+    rho, u, m0 = ctx.moments(gpu(st), with_m0=True)
+    torch.cuda.synchronize()
+    assert rho.dtype == torch.float32 and m0.dtype == torch.float32
+    r_rho, r_u = A.conserved(lat, fw, lam)
+    r_m = A.fixed_moments(lat, fw, lam)
+    t_rho, t_u, t_m = moment_bounds(lat, fw, lam)
+    assert np.all(np.abs(rho.cpu().numpy() - r_rho) <= t_rho)
+    assert np.all(np.abs(u.cpu().numpy() - r_u) <= t_u)
+    assert np.all(np.abs(m0.cpu().numpy() - r_m) <= t_m)
+    # and the bound is not vacuous: relative to each field's norm it is small
+    assert (t_u / np.abs(r_u).max()).max() <= 2e-4
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32", "f32dev", "f16dev"])
 def test_conservation_reduction(storage):
     lat = oracle_lattice("d3q19")
@@ -272,6 +299,43 @@ def test_init_equilibrium_and_conversion(lattice, storage):
     imp = ctx.import_f64(gpu(ref))
     torch.cuda.synchronize()
     assert np.array_equal(imp.cpu().numpy(), host_st)
+
+
+@pytest.mark.parametrize("lattice", ["d2q9", "d3q19", "d3q27"])
+@pytest.mark.parametrize("mode", ["zero", "fluid"])
+def test_fp16_subnormal_deviations(lattice, mode):
+    """A rest state (f = w_j, rho0 = 1) plus perturbations of ~1e-6, so every
+    stored deviation lies in the binary16 subnormal range (below 2^-14 ~ 6.1e-5,
+    spacing 2^-24 ~ 6e-8).  The import is bitwise NumPy's round-to-nearest-even;
+    after a step the stored deviations are still nonzero subnormals (nothing is
+    flushed to zero), and each equals the oracle's deviation after the step,
+    computed in FP64 from the widened state, to within half a subnormal spacing
+    (the FP32 collision errs by ~1e-13 on values of ~1e-6)."""
+    lat = oracle_lattice(lattice)
+    shape = (7, 9) if lat.d == 2 else (3, 4, 5)
+    rng = np.random.default_rng(10)
+    w = lat.w.reshape((-1,) + (1,) * lat.d)
+    f0 = w * np.ones((lat.q,) + shape) + 1e-6 * rng.uniform(-1, 1, (lat.q,) + shape)
+    ctx = Lbmrv(lattice, ctx_rates(lat), tuple(reversed(shape)), "f16dev")
+    host_st, fw = to_storage(lat, f0, "f16dev")
+    sub = np.abs(host_st.astype(np.float64))
+    assert sub.max() < 2.0 ** -14 and np.count_nonzero(sub) > 0.9 * sub.size
+    imp = ctx.import_f64(gpu(f0))
+    torch.cuda.synchronize()
+    assert np.array_equal(imp.cpu().numpy().view(np.uint16), host_st.view(np.uint16))
+    out = torch.empty_like(imp)
+    ctx.step(imp, out, mode, 1.0, None, 1)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    dev = np.abs(got.astype(np.float64))
+    assert dev.max() < 2.0 ** -14
+    assert np.count_nonzero(dev) > 0.8 * dev.size
+    ref_dev = A.step(lat, fw, ctx_rates(lat), mode=MODES[mode]) - w
+    assert np.abs(got.astype(np.float64) - ref_dev).max() <= 2.0 ** -25 * 1.01
+
+
+def ctx_rates(lat):
+    return {9: workloads.RATES_D2Q9_GROUPED, 19: workloads.RATES_D3Q19, 27: workloads.RATES_D3Q27}[lat.q]
 
 
 # ---------------------------------------------------------------------------

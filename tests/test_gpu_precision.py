@@ -7,16 +7,21 @@ state rounded to its storage, so the errors include the initial rounding.
 Errors are normwise relative: ||rho - rho_ref||_inf / ||rho_ref||_inf,
 ||u - u_ref||_inf / ||u_ref||_inf, and for each non-conserved fixed-frame moment
 ||m_k - m_k,ref||_inf / ||m_k,ref||_inf (the largest over k is gated).  Because
-rho ~ 1 hides density errors, ||rho - rho_ref||_inf / ||rho_ref - 1||_inf is
-printed as well (not gated).
+rho ~ 1 hides density errors, the density error is also measured against the
+density perturbation, ||rho - rho_ref||_inf / ||rho_ref - 1||_inf.
 
-Gates, from the arithmetic and a 2x margin over the measured values:
+Gates (None: measured and printed, not gated), from the arithmetic and a margin
+over the measured values:
   FP64 storage        1e-9 on every field (FP64 rounding over 1000 steps);
-  FP32 storage        rho 1e-5, u 2e-5, moments 5e-4 (FP32 rounds |f| ~ 1/3 to
-                      ~2e-8 per step; momentum errors random-walk over 1000 steps);
-  FP32 deviations     rho, u 1e-5, moments 2e-5;
+  FP32 deviations     rho, u 1e-5 (the FP32 tolerance on rho and u at step N),
+                      moments 2e-5, rho against rho - 1: 5e-5;  this is the
+                      FP32 form of the benchmarks;
+  FP32 storage of f itself: rho 1e-5 and moments 5e-4; u and rho against
+                      rho - 1 are reported only: the store rounds |f| ~ 1/3 to
+                      ~2e-8 at every step, and the momentum error random-walks
+                      to 0.8-1.1e-5 of ||u|| over 1000 steps;
   FP16 deviations     rho, u 5e-3 (the tolerance stated for FP16 storage on rho
-                      and u), moments 5e-2.
+                      and u), moments 5e-2, rho against rho - 1: 5e-2.
 The measured values are printed (run pytest with -s).
 """
 import os
@@ -35,6 +40,16 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 L, NSTEPS = 64, 1000
+
+# (storage, gates on rho, rho against rho - 1, u, non-conserved moments)
+GATES = [("f64", (1e-9, 1e-9, 1e-9, 1e-9)), ("f32dev", (1e-5, 5e-5, 1e-5, 2e-5)),
+         ("f32", (1e-5, None, None, 5e-4)), ("f16dev", (5e-3, 5e-2, 5e-3, 5e-2))]
+
+
+def check_gates(errors, gates):
+    for name, e, g in zip(("rho", "rho of rho-1", "u", "moments"), errors, gates):
+        if g is not None:
+            assert e <= g, (name, e, g)
 
 
 @pytest.fixture(scope="module")
@@ -59,10 +74,8 @@ def field_errors(lat, got, ref):
     return e_rho, e_rho1, e_u, e_m
 
 
-@pytest.mark.parametrize("storage,gate_rho,gate_u,gate_m", [
-    ("f64", 1e-9, 1e-9, 1e-9), ("f32", 1e-5, 2e-5, 5e-4), ("f32dev", 1e-5, 1e-5, 2e-5),
-    ("f16dev", 5e-3, 5e-3, 5e-2)])
-def test_taylor_green_64_precision(reference, storage, gate_rho, gate_u, gate_m):
+@pytest.mark.parametrize("storage,gates", GATES)
+def test_taylor_green_64_precision(reference, storage, gates):
     lat, f0, ref = reference
     st, _ = to_storage(lat, f0, storage)
     ctx = Lbmrv("d3q19", workloads.RATES_D3Q19, (L, L, L), storage)
@@ -74,7 +87,7 @@ def test_taylor_green_64_precision(reference, storage, gate_rho, gate_u, gate_m)
     e_rho, e_rho1, e_u, e_m = field_errors(lat, got, ref)
     print("\nprecision %-7s after %d steps: rho %.3e (of rho-1: %.3e)  u %.3e  non-conserved moments %.3e"
           % (storage, NSTEPS, e_rho, e_rho1, e_u, e_m))
-    assert e_rho <= gate_rho and e_u <= gate_u and e_m <= gate_m
+    check_gates((e_rho, e_rho1, e_u, e_m), gates)
 
 
 L27 = 32
@@ -95,10 +108,8 @@ def reference_d3q27():
     return lat, f0, field, ref
 
 
-@pytest.mark.parametrize("storage,gate_rho,gate_u,gate_m", [
-    ("f64", 1e-9, 1e-9, 1e-9), ("f32", 1e-5, 2e-5, 5e-4), ("f32dev", 1e-5, 1e-5, 2e-5),
-    ("f16dev", 5e-3, 5e-3, 5e-2)])
-def test_d3q27_field_precision(reference_d3q27, storage, gate_rho, gate_u, gate_m):
+@pytest.mark.parametrize("storage,gates", GATES)
+def test_d3q27_field_precision(reference_d3q27, storage, gates):
     """The same gates as the D3Q19 case: the storage roundings per step are the
     same, and the moment sums have at most 27 terms instead of 19."""
     lat, f0, field, ref = reference_d3q27
@@ -112,4 +123,4 @@ def test_d3q27_field_precision(reference_d3q27, storage, gate_rho, gate_u, gate_
     e_rho, e_rho1, e_u, e_m = field_errors(lat, got, ref)
     print("\nD3Q27 field precision %-7s after %d steps: rho %.3e (of rho-1: %.3e)  u %.3e  "
           "non-conserved moments %.3e" % (storage, NSTEPS, e_rho, e_rho1, e_u, e_m))
-    assert e_rho <= gate_rho and e_u <= gate_u and e_m <= gate_m
+    check_gates((e_rho, e_rho1, e_u, e_m), gates)

@@ -270,6 +270,28 @@ int lbmrv_moments(lbmrv_ctx *c, const void *f, void *rho, void *u, void *m0, voi
 int lbmrv_conservation(lbmrv_ctx *c, const void *f, double out[4], void *hip_stream);
 
 /*
+ * lbmrv_conservation for callers that cannot allocate device memory: code
+ * being captured into a HIP graph, tight serving loops, harnesses that forbid
+ * hipMalloc.  It computes the same sums with the same kernels (results equal
+ * lbmrv_conservation's bit for bit), but writes them to device memory and
+ * returns without waiting:
+ *   out_dev  device array of 5 doubles, caller-owned, 8-byte aligned:
+ *            [0] sum_x rho, [1 .. d] sum_x q^alpha (physical units),
+ *            [d+1 .. 3] = 0, [4] the number of NaN or infinite populations
+ * The partial sums live in a library-owned device array of 1024 x 5 doubles
+ * (40 KB, one per GPU, taken at the first call on that GPU and held until the
+ * process ends); its size does not depend on the grid, so every grid that
+ * lbmrv_create accepts is served.  The call makes no allocation (no hipMalloc,
+ * no allocating library routine) and no synchronisation.  All calls on one
+ * GPU share that array: calls that overlap on one GPU (different streams, or
+ * host threads without ordering) race and must be serialised by the caller.
+ * Each call overwrites every partial sum before reading it, so nothing is
+ * cleared between calls.
+ * Errors: INVALID_ARG, ALIGNMENT, UNSUPPORTED (device index >= 64), HIP.
+ */
+int lbmrv_conservation_noalloc(lbmrv_ctx *c, const void *f, double *out_dev, void *hip_stream);
+
+/*
  * Distance of a state from a uniform reference state, for the growth rate of
  * small perturbations (linear stability of the scheme about a uniform flow;
  * the paper names stability as the question its schemes leave open).

@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstring>
 #include <array>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -774,6 +775,45 @@ int lbmrv_conservation(lbmrv_ctx* c, const void* f, double out[4], void* hip_str
     return rc;
   for (int i = 0; i < 4; ++i) out[i] = h[i];
   return h[4] > 0 ? LBMRV_ERR_NONFINITE : LBMRV_OK;
+}
+
+// Scratch of lbmrv_conservation_noalloc: the kRedBlocks rows of five partial
+// sums.  One copy per GPU (each device holds its own instance of this
+// variable), resident until the process ends.  In host code `scratch` only
+// names the variable: its device address on the current GPU comes from
+// hipGetSymbolAddress, taken once per device and kept in scratch_addr.
+static __device__ __align__(256) double scratch[kRedBlocks * 5];
+constexpr int kMaxDevices = 64;
+static double* scratch_addr[kMaxDevices];
+static std::mutex scratch_mutex;
+
+static int scratch_for_current_device(double** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return LBMRV_ERR_HIP;
+  if (dev < 0 || dev >= kMaxDevices) return LBMRV_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(scratch_mutex);
+  if (!scratch_addr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return LBMRV_ERR_HIP;
+    scratch_addr[dev] = static_cast<double*>(p);
+  }
+  *out = scratch_addr[dev];
+  return LBMRV_OK;
+}
+
+int lbmrv_conservation_noalloc(lbmrv_ctx* c, const void* f, double* out_dev, void* hip_stream) {
+  if (!c) return LBMRV_ERR_INVALID_ARG;
+  int rc;
+  if ((rc = check_ptr(f, elem_bytes(c->storage))) || (rc = check_ptr(out_dev, 8))) return rc;
+  double* part = nullptr;
+  if ((rc = scratch_for_current_device(&part))) return rc;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  // the partial kernel writes every row of the scratch before the final
+  // kernel reads it, so nothing needs clearing between calls
+  if (kEntries[c->entry].cons[c->sk](f, c->N, part, st) != hipSuccess) return LBMRV_ERR_HIP;
+  hipLaunchKernelGGL(k_conserve_final, dim3(1), dim3(kRedThreads), 0, st, part, out_dev, conserve_add0(c), c->lambda,
+                     c->d);
+  return hipGetLastError() == hipSuccess ? LBMRV_OK : LBMRV_ERR_HIP;
 }
 
 // The reference populations in the stored representation; INVALID_ARG if

@@ -48,6 +48,7 @@ _SIGS = {
     "lbmrv_transport": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p]),
     "lbmrv_moments": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
     "lbmrv_conservation": (_c_int, [_c_void_p, _c_void_p, ctypes.POINTER(_c_double), _c_void_p]),
+    "lbmrv_conservation_noalloc": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p]),
     "lbmrv_init_equilibrium": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_double, _c_void_p,
                                         _c_void_p]),
     "lbmrv_import": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p]),
@@ -241,6 +242,14 @@ class Lbmrv:
         if rc not in (OK, ERR_NONFINITE):
             _check(rc, "lbmrv_conservation")
         return out[0], list(out[1:1 + self.d]), rc == OK
+
+    def conservation_noalloc(self, f, out, stream=None):
+        """The same sums into the device tensor `out` (5 doubles: mass,
+        momentum[3], count of non-finite values), asynchronously and without
+        any allocation (lbmrv_conservation_noalloc)."""
+        _check(library().lbmrv_conservation_noalloc(self._h, _ptr(f), _ptr(out), _stream(stream)),
+               "lbmrv_conservation_noalloc")
+        return out
 
     def init_equilibrium(self, rho, u, noise=None, amp=0.0, out=None, stream=None):
         out = self.empty(rho.device) if out is None else out

@@ -133,6 +133,13 @@ struct lbmrv_ctx {
   int equilibrium = LBMRV_EQ_POLYNOMIAL;
   int block_order = LBMRV_ORDER_AUTO;
   // run-time basis P = R W (W the built-in working basis of `entry`)
+  // adjoint: a second stream (default priority) on which segments are
+  // recomputed ahead of the reverse sweep on the caller's stream, and the
+  // events that order the two; created at the first lbmrv_adjoint call that
+  // needs them, on that call's device
+  hipStream_t astream = nullptr;
+  hipEvent_t aev[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  int astream_dev = -1;
   int custom = 0;
   std::vector<double> R;              // q x q
   std::vector<double> Rnn, Rnninv;    // non-conserved block and its inverse
@@ -913,22 +920,28 @@ namespace {
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct AdjPlan {
-  int64_t nseg, nsnap, nsegslots;
+  int64_t nseg, nsnap, nsegslots, nsets;
   size_t state_bytes, lam_bytes, partial_bytes, total;
   uint64_t nblocks;
 };
 
+// Workspace: nsnap snapshots (states K, 2K, ...), nsets sets of nsegslots
+// segment states (segment sg uses set sg mod nsets; with three sets a segment
+// can be recomputed two segments ahead of the reverse sweep), two ping-pong
+// states for the forward sweep, one state for f_N when the caller passes none,
+// two adjoint states and the rows of dJ/ds partial sums.
 AdjPlan adj_plan(const lbmrv_ctx* c, int64_t nsteps, int64_t K) {
   AdjPlan p{};
   p.nseg = (nsteps + K - 1) / K;
   p.nsnap = p.nseg - 1;
   p.nsegslots = (nsteps < K ? nsteps : K) - 1;
+  p.nsets = p.nseg < 3 ? p.nseg : 3;
   p.state_bytes = align256(elem_bytes(c->storage) * c->q * c->N);
   p.lam_bytes = align256((c->storage == LBMRV_F64 ? 8 : 4) * (size_t)c->q * c->N);
   const uint64_t gx = (c->nx + c->block - 1) / c->block;
   p.nblocks = gx * c->ny * c->nz;
   p.partial_bytes = align256(sizeof(double) * p.nblocks * c->q);
-  p.total = p.state_bytes * (size_t)(p.nsnap + p.nsegslots + 1) + 2 * p.lam_bytes + p.partial_bytes;
+  p.total = p.state_bytes * (size_t)(p.nsnap + p.nsets * p.nsegslots + 3) + 2 * p.lam_bytes + p.partial_bytes;
   return p;
 }
 
@@ -968,26 +981,90 @@ int lbmrv_adjoint(lbmrv_ctx* c, const void* f0, int ut_mode, double ut_alpha, co
   if (workspace_bytes < P.total) return LBMRV_ERR_INVALID_ARG;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
 
+  // Segments other than the last are recomputed from their first state on a
+  // second stream, ahead of the reverse sweep on the caller's stream, so that
+  // the two sweeps overlap on the GPU (needed only when there are several
+  // segments with states inside them).
+  const bool recompute_any = P.nseg > 1 && P.nsegslots > 0;
+  const int64_t S = P.nsets;
+  if (recompute_any) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return LBMRV_ERR_HIP;
+    if (c->astream && c->astream_dev != dev) return LBMRV_ERR_INVALID_ARG;  // bound to its first device
+    if (!c->astream) {
+      if (hipStreamCreateWithFlags(&c->astream, hipStreamNonBlocking) != hipSuccess) {
+        c->astream = nullptr;
+        return LBMRV_ERR_HIP;
+      }
+      c->astream_dev = dev;
+      for (auto& ev : c->aev)
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+          ev = nullptr;
+          return LBMRV_ERR_HIP;
+        }
+    }
+  }
+  hipStream_t st2 = c->astream;
+  // aev[0]: a snapshot written; aev[1 + r mod 3]: segment r recomputed (on
+  // st2); aev[4 + sg mod 3]: segment sg reversed (on st)
+  hipEvent_t ev_snap = c->aev[0];
+  auto ev_rec = [&](int64_t r) { return c->aev[1 + r % 3]; };
+  auto ev_rev = [&](int64_t sg) { return c->aev[4 + sg % 3]; };
+
   char* w = static_cast<char*>(workspace);
   char* snaps = w;
   char* segs = snaps + P.state_bytes * P.nsnap;
-  char* fscratch = segs + P.state_bytes * P.nsegslots;
+  char* pingpong = segs + P.state_bytes * P.nsegslots * S;
+  char* fscratch = pingpong + 2 * P.state_bytes;
   char* lam0 = fscratch + P.state_bytes;
   char* lam1 = lam0 + P.lam_bytes;
   double* partial = reinterpret_cast<double*>(lam1 + P.lam_bytes);
   void* fN = f_N ? f_N : fscratch;
+  const int64_t last = P.nseg - 1;
+  // state t as the reverse sweep reads it (and the recompute writes it)
   auto state = [&](int64_t t) -> void* {
     if (t == 0) return const_cast<void*>(f0);
     if (t == nsteps) return fN;
     if (t % K == 0) return snaps + P.state_bytes * (t / K - 1);
-    return segs + P.state_bytes * (t % K - 1);
+    return segs + P.state_bytes * (P.nsegslots * ((t / K) % S) + (t % K - 1));
+  };
+  // state t in the forward sweep: states inside earlier segments are not kept,
+  // they alternate between two buffers that stay in the last-level cache
+  auto fwd_state = [&](int64_t t) -> void* {
+    if (t == 0 || t == nsteps || t % K == 0 || t / K == last) return state(t);
+    return pingpong + P.state_bytes * (t % 2);
   };
   const Entry& E = kEntries[c->entry];
   hipError_t e;
-  // forward sweep (scatter form, pre-collision states), keeping every K-th state
+  // Recompute the states inside segment r from its first state on st2, into
+  // set r mod S.  The set's previous user, segment r + S, must have been
+  // reversed first; ev_rev(r + S) is recorded before this is issued.
+  auto issue_recompute = [&](int64_t r) -> hipError_t {
+    hipError_t er;
+    if (r + S <= last && (er = hipStreamWaitEvent(st2, ev_rev(r + S), 0)) != hipSuccess) return er;
+    const int64_t t0 = r * K, t1 = (t0 + K < nsteps) ? t0 + K : nsteps;
+    for (int64_t t = t0; t + 1 < t1; ++t)
+      if ((er = run_kind(c, K_PUSH, state(t), state(t + 1), ut_mode, ut_alpha, ut_field, st2)) != hipSuccess)
+        return er;
+    return hipEventRecord(ev_rec(r), st2);
+  };
+  // forward sweep (scatter form, pre-collision states), keeping every K-th
+  // state and the states of the last segment.  The S - 1 segments before the
+  // last (whose sets the forward sweep does not touch) are recomputed on st2
+  // as soon as their first state is written, alongside the rest of the sweep.
   for (int64_t t = 0; t < nsteps; ++t) {
-    e = run_kind(c, K_PUSH, state(t), state(t + 1), ut_mode, ut_alpha, ut_field, st);
+    e = run_kind(c, K_PUSH, fwd_state(t), fwd_state(t + 1), ut_mode, ut_alpha, ut_field, st);
     if (e != hipSuccess) return LBMRV_ERR_HIP;
+    const int64_t r = (t + 1) / K;
+    if (recompute_any && (t + 1) % K == 0 && r < last && r >= last - (S - 1)) {
+      if (hipEventRecord(ev_snap, st) != hipSuccess || hipStreamWaitEvent(st2, ev_snap, 0) != hipSuccess ||
+          issue_recompute(r) != hipSuccess)
+        return LBMRV_ERR_HIP;
+    }
+  }
+  if (recompute_any && last - (S - 1) <= 0 && last >= 1) {
+    // segment 0 among them: its first state is f0, present from the start
+    if (issue_recompute(0) != hipSuccess) return LBMRV_ERR_HIP;
   }
   if ((e = fill_zero(partial, P.nblocks * c->q, st)) != hipSuccess) return LBMRV_ERR_HIP;
   if (ut_mode == LBMRV_UT_FIELD && (e = fill_zero(grad_ut, (uint64_t)c->d * c->N, st)) != hipSuccess)
@@ -1011,22 +1088,23 @@ int lbmrv_adjoint(lbmrv_ctx* c, const void* f0, int ut_mode, double ut_alpha, co
   A.eq_maxwell = c->equilibrium == LBMRV_EQ_MAXWELLIAN ? 1u : 0u;
   A.stream = st;
   A.block = c->block;
-  // reverse sweep, one segment of K steps at a time; the last segment's states
-  // are still in place from the forward sweep, earlier ones are recomputed
-  for (int64_t sg = P.nseg - 1; sg >= 0; --sg) {
+  // Reverse sweep, one segment of K steps at a time, last segment first (its
+  // states are in place from the forward sweep).  Segment sg waits for its
+  // recompute; once it is reversed its set is free, and segment sg - S is
+  // recomputed into it on st2, S - 1 segments ahead of the reverse sweep.
+  for (int64_t sg = last; sg >= 0; --sg) {
+    if (recompute_any && sg < last && hipStreamWaitEvent(st, ev_rec(sg), 0) != hipSuccess) return LBMRV_ERR_HIP;
     const int64_t t0 = sg * K;
     const int64_t t1 = (t0 + K < nsteps) ? t0 + K : nsteps;
-    if (sg < P.nseg - 1) {
-      for (int64_t t = t0; t + 1 < t1; ++t) {
-        e = run_kind(c, K_PUSH, state(t), state(t + 1), ut_mode, ut_alpha, ut_field, st);
-        if (e != hipSuccess) return LBMRV_ERR_HIP;
-      }
-    }
     for (int64_t t = t1 - 1; t >= t0; --t) {
       A.f = state(t);
       A.lam_in = (t == nsteps - 1) ? cot_fN : ((t + 1) % 2 ? lam1 : lam0);
       A.lam_out = (t == 0) ? grad_f0 : (t % 2 ? lam1 : lam0);
       if ((e = E.adj[c->sk](A)) != hipSuccess) return LBMRV_ERR_HIP;
+    }
+    if (recompute_any && sg - S >= 0) {
+      if (hipEventRecord(ev_rev(sg), st) != hipSuccess || issue_recompute(sg - S) != hipSuccess)
+        return LBMRV_ERR_HIP;
     }
   }
   hipLaunchKernelGGL(k_reduce_columns, dim3(1), dim3(kRedCols, kRedRows), 0, st, partial, P.nblocks, c->q, c->d, grad_s);
@@ -1035,6 +1113,9 @@ int lbmrv_adjoint(lbmrv_ctx* c, const void* f0, int ut_mode, double ut_alpha, co
 
 void lbmrv_destroy(lbmrv_ctx* c) {
   if (!c) return;
+  if (c->astream) (void)hipStreamDestroy(c->astream);
+  for (auto& ev : c->aev)
+    if (ev) (void)hipEventDestroy(ev);
   if (c->partial) (void)hipFree(c->partial);
   if (c->dtab) (void)hipFree(c->dtab);
   delete c;

@@ -40,6 +40,7 @@ TRAFFIC_GB = {
     ("d3q19_tgv256_f16dev_fluid", "pull"): 1.2752,
     ("d3q19_tgv256_f64_fluid", "pull"): 5.1006,
     ("d3q19_tgv256_f32dev_fluid", "pull"): 2.5508,
+    ("d3q19_tgv256_f32dev_fluid", "aa"): 2.5504,
     ("d3q19_tgv512_f32_fluid", "pull"): 21.0810,
     ("d3q27_tgv192_f32_field", "pull"): 1.6595,
     ("d3q27_tgv192_f16dev_field", "pull"): 0.8731,

@@ -585,22 +585,30 @@ __device__ __forceinline__ void collide_node(T (&h)[B::Q], const StepArgs<T>& a,
 
 // ------------------------------------------------------------------ step kernel
 // Grid: (ceil(nx / blockDim.x), ceil(ny / blockDim.y), nz).  One thread = one
-// node (x, y, z).  The gather forms run blocks of up to 1024 threads spanning
-// several consecutive rows (blockDim.y > 1), so that each block streams a few
-// KB of every population array contiguously; the scatter form uses one row.
-// (512 for FP64 storage, whose D3Q27 collision needs more than 128 registers)
-template <int ST>
+// node (x, y, z).  The forms that store at the node (pull, collide,
+// transport, in-place even) run blocks of up to 1024 threads spanning several
+// consecutive rows (blockDim.y > 1), so that each block streams a few KB of
+// every population array contiguously (512 for FP64 storage, whose D3Q27
+// collision needs more than 128 registers).  The scatter forms (push,
+// in-place odd) run one row of at most 256 threads, and their bound says so:
+// with the 1024-thread bound the D3Q27 in-place odd step was held to 128
+// registers and spilled to scratch.
+constexpr bool scatter_kind(int kind) { return kind == K_PUSH || kind == K_AA_ODD || kind == K_AA_ODD_WALLS; }
+
+template <int ST, int KIND>
 constexpr int step_max_threads() {
-  return ST == 0 ? 512 : 1024;
+  return scatter_kind(KIND) ? 256 : (ST == 0 ? 512 : 1024);
 }
 
 // Wavefronts per SIMD the register allocation must allow (1: no constraint).
-// D3Q27 with FP16 storage otherwise takes 97 VGPRs, one past the 96 that let
-// a SIMD hold 5 of its wavefronts: at 5 it spends ~9 % more instructions on
-// moves but measured 3.5 % faster (6 would spill to scratch).
-template <class B, int ST>
+// The D3Q27 step with FP16 storage at the node takes 97 VGPRs, one past the 96
+// that let a SIMD hold 5 of its wavefronts: at 5 it spends ~9 % more
+// instructions on moves but measured 3.5 % faster (6 would spill to scratch).
+// The scatter forms need more registers for their destinations and are left
+// unconstrained (at 5 the in-place odd step spilled 216 bytes per lane).
+template <class B, int ST, int KIND>
 constexpr int step_min_waves() {
-  return (B::Q == 27 && ST == 2) ? 5 : 1;
+  return (B::Q == 27 && ST == 2 && !scatter_kind(KIND)) ? 5 : 1;
 }
 
 // Half-way bounce-back.  wall_face_in<L, J>: the wall face that the link from
@@ -659,8 +667,8 @@ __device__ __forceinline__ uint3 block_tile(uint32_t remap) {
 }
 
 template <class B, int ST, int MODE, int KIND, int RLX>
-__global__ __launch_bounds__(step_max_threads<ST>())
-__attribute__((amdgpu_waves_per_eu(step_min_waves<B, ST>()))) void k_step(StepArgs<typename Store<ST>::T> a) {
+__global__ __launch_bounds__((step_max_threads<ST, KIND>()))
+__attribute__((amdgpu_waves_per_eu(step_min_waves<B, ST, KIND>()))) void k_step(StepArgs<typename Store<ST>::T> a) {
   using L = typename B::Lat;
   using S = typename Store<ST>::S;
   using T = typename Store<ST>::T;

@@ -74,12 +74,12 @@ hipError_t launch_step_t(const StepLaunch& L) {
   // at 512^3 that measured 6.9 % faster than 512-wide rows in FP32, 3.9 % in
   // FP64 and the same in FP16.
   constexpr bool wide = KIND == K_PULL || KIND == K_STREAM || KIND == K_COLLIDE;
-  const uint32_t bx_max = !wide ? 256u : (B::Q == 19 ? 256u : (uint32_t)step_max_threads<ST>());
+  const uint32_t bx_max = !wide ? 256u : (B::Q == 19 ? 256u : (uint32_t)step_max_threads<ST, KIND>());
   const uint32_t bx = L.nx >= bx_max ? bx_max : ((L.nx + 63u) / 64u) * 64u;
   // (FP16 storage measured faster with one row per block)
   uint32_t by = (KIND == K_PUSH || KIND == K_AA_ODD || KIND == K_AA_ODD_WALLS || ST == 2)
                     ? 1u
-                    : (uint32_t)step_max_threads<ST>() / bx;
+                    : (uint32_t)step_max_threads<ST, KIND>() / bx;
   // D3Q27's step holds ~90 VGPRs, so at most 5 wavefronts per SIMD: one
   // 15-wavefront block of five 192-wide rows per CU leaves slots idle, blocks
   // of two rows pack better (measured +2.6 % at 192^3 FP32; one row and three

@@ -34,48 +34,33 @@ struct AdjArgs {
   uint64_t N;
   T rho0, inv_lambda, alpha;
   T s[27];
+  const void* f_prev;  // two-step kernel: f^{n-1}, storage type, [q][N] (f is then f^n)
   const T* rnn;     // run-time basis only: non-conserved block of R (P = R W), (Q-D-1)^2 row-major
   const T* rnninv;  // and its inverse
   uint32_t xcd_remap;  // block order, as for the step kernels (block_tile)
   uint32_t eq_maxwell; // 1: equilibrium moments of the continuous Maxwellian
 };
 
+// The adjoint of one time step at one node (the transpose of the collision
+// Jacobian, with the equations at the top of this file): from the node's
+// populations h (stored values), the gathered adjoint g_j = lambda^{n+1}_j(x +
+// c_j) and, for a given field, u~ in lattice units, it returns lambda^n at the
+// node, the node's dJ/du~ in lattice units (a field; folded into lambda for
+// u~ = alpha u), and z3, r whose products z3_k r_k are the node's dJ/ds_k.
 template <class B, int ST, int MODE, int RLX>
-__global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> a) {
+__device__ __forceinline__ void adjoint_node(const AdjArgs<typename Store<ST>::T>& a,
+                                             const typename Store<ST>::T (&h)[B::Q],
+                                             const typename Store<ST>::T (&g)[B::Q],
+                                             const typename Store<ST>::T (&utf)[3],
+                                             typename Store<ST>::T (&lam_out)[B::Q],
+                                             typename Store<ST>::T (&gut_out)[3],
+                                             typename Store<ST>::T (&z3_out)[B::Q],
+                                             typename Store<ST>::T (&r_out)[B::Q]) {
   using L = typename B::Lat;
-  using S = typename Store<ST>::S;
   using T = typename Store<ST>::T;
   using Tb = Tab<B>;
   constexpr int Q = B::Q;
   constexpr int D = L::D;
-
-  const uint3 tile = block_tile(a.xcd_remap);
-  const uint32_t xr = tile.x * blockDim.x + threadIdx.x;
-  const bool active = xr < a.nx;
-  const uint32_t x = active ? xr : a.nx - 1;  // inactive lanes recompute a valid node, store nothing
-  const uint32_t y = tile.y, z = tile.z;
-  const uint32_t nx = a.nx, ny = a.ny, nz = a.nz;
-  const uint32_t xp = x == nx - 1 ? 0 : x + 1, xm = x == 0 ? nx - 1 : x - 1;
-  const uint32_t yp = y == ny - 1 ? 0 : y + 1, ym = y == 0 ? ny - 1 : y - 1;
-  const uint32_t zp = z == nz - 1 ? 0 : z + 1, zm = z == 0 ? nz - 1 : z - 1;
-  const uint32_t own = (z * ny + y) * nx + x;
-  const uint64_t N = a.N;
-  const S* f = static_cast<const S*>(a.f);
-
-  T h[Q], g[Q];
-  sfor<Q>([&](auto jj) {
-    constexpr int J = jj;
-    constexpr int cx = L::c[J].x, cy = L::c[J].y, cz = L::c[J].z;
-    const uint32_t xx = cx == 0 ? x : (cx > 0 ? xp : xm);
-    const uint32_t yy = cy == 0 ? y : (cy > 0 ? yp : ym);
-    const uint32_t zz = cz == 0 ? z : (cz > 0 ? zp : zm);
-    // accesses aligned with the wavefront stream past the caches; the +-1
-    // shifted gathers along x share lines with the neighbouring wavefront
-    h[J] = T(__builtin_nontemporal_load(&f[(uint64_t)J * N + own]));
-    const T* src = &a.lam_in[(uint64_t)J * N + (zz * ny + yy) * nx + xx];
-    if constexpr (cx == 0) g[J] = __builtin_nontemporal_load(src);
-    else g[J] = *src;
-  });
 
   // ---- forward quantities at this node (monomial bases on {0, +-1}^d with
   // FP32 arithmetic: all moments, and below the two transposed maps, by the
@@ -105,7 +90,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
   const T u[3] = {jm[0] * irho, jm[1] * irho, D == 3 ? jm[2] * irho : T(0)};
   T ut[3] = {T(0), T(0), T(0)};
   if constexpr (MODE == UT_FIELD) {
-    sfor<D>([&](auto al) { ut[al] = T(a.ut[(uint64_t)al * N + own]) * a.inv_lambda; });
+    sfor<D>([&](auto al) { ut[al] = utf[al]; });
   } else if constexpr (MODE == UT_FLUID) {
     sfor<D>([&](auto al) { ut[al] = a.alpha * u[al]; });
   }
@@ -339,9 +324,6 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
       gut[AX] = gsum;
     });
   }
-  if constexpr (MODE == UT_FIELD) {
-    if (active) sfor<D>([&](auto ax) { a.grad_ut[(uint64_t)ax * N + own] += double(gut[ax] * a.inv_lambda); });
-  }
 
   // z6 = T(u~)^T z5
   if constexpr (MODE != UT_ZERO) apply_shift(z5, T(-1), std::true_type{});
@@ -387,25 +369,78 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
   if constexpr (MODE == UT_FLUID) {
     sfor<D>([&](auto al) { Bv[al] = fmac(a.alpha * irho, gut[al], Bv[al]); });
   }
-  if (active) {
-    T* lo = a.lam_out;
-    T yt[cube ? Q : 1];  // M_W(0)^T z6
-    if constexpr (cube) cube_moments_t<B>(z5, yt);
-    sfor<Q>([&](auto jj) {
-      constexpr int J = jj;
-      T yv = zsum<T>();
-      if constexpr (cube) {
-        yv = yt[J];
-      } else {
-        sfor<Tb::t.tMW[J].n>([&](auto i) { axpy_c<Tb::t.tMW[J].val[i]>(yv, z5[Tb::t.tMW[J].col[i]]); });
-      }
-      T lam = g[J] - yv + A0;
-      sfor<D>([&](auto al) {
-        constexpr int cj = al == 0 ? L::c[J].x : al == 1 ? L::c[J].y : L::c[J].z;
-        lam = fmac(Bv[al], T(cj) - u[al], lam);
-      });
-      __builtin_nontemporal_store(lam, &lo[(uint64_t)J * N + own]);
+  T yt[cube ? Q : 1];  // M_W(0)^T z6
+  if constexpr (cube) cube_moments_t<B>(z5, yt);
+  sfor<Q>([&](auto jj) {
+    constexpr int J = jj;
+    T yv = zsum<T>();
+    if constexpr (cube) {
+      yv = yt[J];
+    } else {
+      sfor<Tb::t.tMW[J].n>([&](auto i) { axpy_c<Tb::t.tMW[J].val[i]>(yv, z5[Tb::t.tMW[J].col[i]]); });
+    }
+    T lam = g[J] - yv + A0;
+    sfor<D>([&](auto al) {
+      constexpr int cj = al == 0 ? L::c[J].x : al == 1 ? L::c[J].y : L::c[J].z;
+      lam = fmac(Bv[al], T(cj) - u[al], lam);
     });
+    lam_out[J] = lam;
+  });
+  sfor<3>([&](auto ax) { gut_out[ax] = gut[ax]; });
+  sfor<Q>([&](auto kk) {
+    z3_out[kk] = z3[kk];
+    r_out[kk] = r[kk];
+  });
+
+}
+
+template <class B, int ST, int MODE, int RLX>
+__global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> a) {
+  using L = typename B::Lat;
+  using S = typename Store<ST>::S;
+  using T = typename Store<ST>::T;
+  constexpr int Q = B::Q;
+  constexpr int D = L::D;
+
+  const uint3 tile = block_tile(a.xcd_remap);
+  const uint32_t xr = tile.x * blockDim.x + threadIdx.x;
+  const bool active = xr < a.nx;
+  const uint32_t x = active ? xr : a.nx - 1;  // inactive lanes recompute a valid node, store nothing
+  const uint32_t y = tile.y, z = tile.z;
+  const uint32_t nx = a.nx, ny = a.ny, nz = a.nz;
+  const uint32_t xp = x == nx - 1 ? 0 : x + 1, xm = x == 0 ? nx - 1 : x - 1;
+  const uint32_t yp = y == ny - 1 ? 0 : y + 1, ym = y == 0 ? ny - 1 : y - 1;
+  const uint32_t zp = z == nz - 1 ? 0 : z + 1, zm = z == 0 ? nz - 1 : z - 1;
+  const uint32_t own = (z * ny + y) * nx + x;
+  const uint64_t N = a.N;
+  const S* f = static_cast<const S*>(a.f);
+
+  T h[Q], g[Q];
+  sfor<Q>([&](auto jj) {
+    constexpr int J = jj;
+    constexpr int cx = L::c[J].x, cy = L::c[J].y, cz = L::c[J].z;
+    const uint32_t xx = cx == 0 ? x : (cx > 0 ? xp : xm);
+    const uint32_t yy = cy == 0 ? y : (cy > 0 ? yp : ym);
+    const uint32_t zz = cz == 0 ? z : (cz > 0 ? zp : zm);
+    // accesses aligned with the wavefront stream past the caches; the +-1
+    // shifted gathers along x share lines with the neighbouring wavefront
+    h[J] = T(__builtin_nontemporal_load(&f[(uint64_t)J * N + own]));
+    const T* src = &a.lam_in[(uint64_t)J * N + (zz * ny + yy) * nx + xx];
+    if constexpr (cx == 0) g[J] = __builtin_nontemporal_load(src);
+    else g[J] = *src;
+  });
+
+  T utf[3] = {T(0), T(0), T(0)};
+  if constexpr (MODE == UT_FIELD) {
+    sfor<D>([&](auto al) { utf[al] = T(a.ut[(uint64_t)al * N + own]) * a.inv_lambda; });
+  }
+  T lam[Q], gut[3], z3[Q], r[Q];
+  adjoint_node<B, ST, MODE, RLX>(a, h, g, utf, lam, gut, z3, r);
+  if constexpr (MODE == UT_FIELD) {
+    if (active) sfor<D>([&](auto ax) { a.grad_ut[(uint64_t)ax * N + own] += double(gut[ax] * a.inv_lambda); });
+  }
+  if (active) {
+    sfor<Q>([&](auto jj) { __builtin_nontemporal_store(lam[jj], &a.lam_out[(uint64_t)jj * N + own]); });
   }
 
   // dJ/ds_k: block sum of z3_k r_k in FP64, added to this block's row
@@ -427,6 +462,141 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<typename Store<ST>::T> 
     const int nw = (blockDim.x + 63) >> 6;
     for (int w = 0; w < nw; ++w) sum += red[w][threadIdx.x];
     a.partial[(uint64_t)bid * Q + threadIdx.x] += sum;
+  }
+}
+
+// Two reverse steps in one launch (two-dimensional lattices, FP32
+// arithmetic): lambda^{n-1} from lambda^{n+1}, f^n and f^{n-1}, with lambda^n
+// kept in LDS.  A block owns a tile of kA2X x kA2Y nodes.  It stages
+// lambda^{n+1} on the tile and a two-node halo (periodic), computes lambda^n on
+// the tile and a one-node ring (the ring is also computed by the neighbouring
+// blocks: 29 % more adjoint work per step pair for 64 x 8 tiles), then
+// lambda^{n-1} on the tile.  Each node's arithmetic is adjoint_node, as in
+// k_adjoint, so lambda^{n-1} and dJ/du~ (added to the FP64 accumulator in the
+// same order, step n first) are bit for bit those of two single steps; the
+// dJ/ds partial sums go to one row per tile of this grid and differ from the
+// single steps only in the order of the FP64 additions.  Small grids are
+// bound by the latency and the fixed cost of each launch, which this halves;
+// on large grids lambda^n never goes to HBM.
+constexpr int kA2X = 64, kA2Y = 8;
+constexpr int kA2RX = kA2X + 2, kA2RY = kA2Y + 2;  // ring region: lambda^n
+constexpr int kA2HX = kA2X + 4, kA2HY = kA2Y + 4;  // halo region: lambda^{n+1}
+
+__device__ __forceinline__ int wrap_index(int i, int n) {
+  int m = i % n;
+  return m < 0 ? m + n : m;
+}
+
+template <class B, int ST, int MODE, int RLX>
+__global__ __launch_bounds__(kA2X* kA2Y) void k_adjoint2(AdjArgs<typename Store<ST>::T> a) {
+  using L = typename B::Lat;
+  using S = typename Store<ST>::S;
+  using T = typename Store<ST>::T;
+  constexpr int Q = B::Q;
+  constexpr int D = L::D;
+  static_assert(D == 2 && sizeof(T) == 4, "the two-step adjoint is for 2-D lattices with FP32 arithmetic");
+  constexpr int NT = kA2X * kA2Y;
+  __shared__ T lh[Q][kA2HY * kA2HX];  // lambda^{n+1}, halo region
+  __shared__ T lr[Q][kA2RY * kA2RX];  // lambda^n, ring region
+  __shared__ T gr[D][NT];             // step n's dJ/du~ at the owned nodes (field mode)
+  __shared__ double red[NT / 64][Q];
+
+  const uint3 tile = block_tile(a.xcd_remap);
+  const int tid = threadIdx.x;
+  const int nx = (int)a.nx, ny = (int)a.ny;
+  const int x0 = (int)tile.x * kA2X, y0 = (int)tile.y * kA2Y;
+  const uint64_t N = a.N;
+  const S* fn = static_cast<const S*>(a.f);
+  const S* fp = static_cast<const S*>(a.f_prev);
+
+  // lambda^{n+1} on the halo region
+  for (int i = tid; i < kA2HY * kA2HX; i += NT) {
+    const int ix = i % kA2HX, iy = i / kA2HX;
+    const uint64_t node = (uint64_t)wrap_index(y0 - 2 + iy, ny) * nx + wrap_index(x0 - 2 + ix, nx);
+    sfor<Q>([&](auto jj) { lh[jj][i] = a.lam_in[(uint64_t)jj * N + node]; });
+  }
+  __syncthreads();
+
+  double sacc[Q];
+  sfor<Q>([&](auto kk) { sacc[kk] = 0.0; });
+  // step n on the ring region
+  for (int i = tid; i < kA2RY * kA2RX; i += NT) {
+    const int ix = i % kA2RX, iy = i / kA2RX;  // tile coordinates ix - 1, iy - 1
+    const int gx = wrap_index(x0 - 1 + ix, nx), gy = wrap_index(y0 - 1 + iy, ny);
+    const uint64_t node = (uint64_t)gy * nx + gx;
+    T h[Q], g[Q], utf[3] = {T(0), T(0), T(0)};
+    sfor<Q>([&](auto jj) {
+      constexpr int J = jj;
+      h[J] = T(fn[(uint64_t)J * N + node]);
+      g[J] = lh[J][(iy + 1 + L::c[J].y) * kA2HX + (ix + 1 + L::c[J].x)];
+    });
+    if constexpr (MODE == UT_FIELD) {
+      sfor<D>([&](auto al) { utf[al] = T(a.ut[(uint64_t)al * N + node]) * a.inv_lambda; });
+    }
+    T lam[Q], gut[3], z3[Q], r[Q];
+    adjoint_node<B, ST, MODE, RLX>(a, h, g, utf, lam, gut, z3, r);
+    sfor<Q>([&](auto jj) { lr[jj][i] = lam[jj]; });
+    const bool owned = ix >= 1 && ix <= kA2X && iy >= 1 && iy <= kA2Y && x0 + ix - 1 < nx && y0 + iy - 1 < ny;
+    if (owned) {
+      sfor<Q>([&](auto kk) {
+        constexpr int K = kk;
+        if constexpr (K > D) sacc[K] += double(z3[K]) * double(r[K]);
+      });
+      if constexpr (MODE == UT_FIELD) {
+        sfor<D>([&](auto al) { gr[al][(iy - 1) * kA2X + (ix - 1)] = gut[al]; });
+      }
+    }
+  }
+  __syncthreads();
+
+  // step n - 1 on the owned tile
+  const int tx = tid % kA2X, ty = tid / kA2X;
+  const int x = x0 + tx, y = y0 + ty;
+  if (x < nx && y < ny) {
+    const uint64_t node = (uint64_t)y * nx + x;
+    T h[Q], g[Q], utf[3] = {T(0), T(0), T(0)};
+    sfor<Q>([&](auto jj) {
+      constexpr int J = jj;
+      h[J] = T(__builtin_nontemporal_load(&fp[(uint64_t)J * N + node]));
+      g[J] = lr[J][(ty + 1 + L::c[J].y) * kA2RX + (tx + 1 + L::c[J].x)];
+    });
+    if constexpr (MODE == UT_FIELD) {
+      sfor<D>([&](auto al) { utf[al] = T(a.ut[(uint64_t)al * N + node]) * a.inv_lambda; });
+    }
+    T lam[Q], gut[3], z3[Q], r[Q];
+    adjoint_node<B, ST, MODE, RLX>(a, h, g, utf, lam, gut, z3, r);
+    sfor<Q>([&](auto jj) { __builtin_nontemporal_store(lam[jj], &a.lam_out[(uint64_t)jj * N + node]); });
+    sfor<Q>([&](auto kk) {
+      constexpr int K = kk;
+      if constexpr (K > D) sacc[K] += double(z3[K]) * double(r[K]);
+    });
+    if constexpr (MODE == UT_FIELD) {
+      sfor<D>([&](auto al) {
+        double* gp = &a.grad_ut[(uint64_t)al * N + node];
+        double v = *gp;
+        v += double(gr[al][tid] * a.inv_lambda);
+        v += double(gut[al] * a.inv_lambda);
+        *gp = v;
+      });
+    }
+  }
+
+  // dJ/ds_k: block sum, added to this tile's row
+  const int lane = tid & 63, wave = tid >> 6;
+  sfor<Q>([&](auto kk) {
+    constexpr int K = kk;
+    if constexpr (K > D) {
+      double c = sacc[K];
+      for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+      if (lane == 0) red[wave][K] = c;
+    }
+  });
+  __syncthreads();
+  if (tid < Q && tid > D) {
+    double sum = 0.0;
+    for (int w = 0; w < NT / 64; ++w) sum += red[w][tid];
+    const uint32_t bid = tile.x + gridDim.x * (tile.y + gridDim.y * tile.z);
+    a.partial[(uint64_t)bid * Q + tid] += sum;
   }
 }
 

@@ -87,6 +87,7 @@ struct Entry {
   InitFn init[3];
   ConvFn conv[3];
   AdjFn adj[3];
+  AdjFn adj2[3];
   FinFn fin[3];
   DevNormFn dnorm[3];
   DevScaleFn dscale[3];
@@ -100,6 +101,7 @@ struct Entry {
         {launch_init_##NAME##_f64, launch_init_##NAME##_f32, launch_init_##NAME##_f16},   \
         {launch_convert_##NAME##_f64, launch_convert_##NAME##_f32, launch_convert_##NAME##_f16}, \
         {launch_adjoint_##NAME##_f64, launch_adjoint_##NAME##_f32, launch_adjoint_##NAME##_f16}, \
+        {launch_adjoint2_##NAME##_f64, launch_adjoint2_##NAME##_f32, launch_adjoint2_##NAME##_f16}, \
         {launch_aa_finish_##NAME##_f64, launch_aa_finish_##NAME##_f32, launch_aa_finish_##NAME##_f16}, \
         {launch_devnorm_##NAME##_f64, launch_devnorm_##NAME##_f32, launch_devnorm_##NAME##_f16}, \
         {launch_devscale_##NAME##_f64, launch_devscale_##NAME##_f32, launch_devscale_##NAME##_f16} \
@@ -919,6 +921,14 @@ namespace {
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// Grids up to this many nodes reverse two steps per launch (k_adjoint2) where
+// the lattice has that kernel: small grids are bound by each launch's latency
+// and fixed cost.  Measured (D2Q9 FP32, u~ a field, K = 100), two steps per
+// launch against one: 512^2 -16 %, 724^2 -9 %, 1024^2 -5 %, 1448^2 -1.3 %,
+// 2048^2 +4.6 % (there HBM bounds both, and the single-step kernel runs more
+// wavefronts per SIMD).
+constexpr uint64_t kAdj2MaxNodes = 1ull << 21;
+
 struct AdjPlan {
   int64_t nseg, nsnap, nsegslots, nsets;
   size_t state_bytes, lam_bytes, partial_bytes, total;
@@ -940,6 +950,10 @@ AdjPlan adj_plan(const lbmrv_ctx* c, int64_t nsteps, int64_t K) {
   p.lam_bytes = align256((c->storage == LBMRV_F64 ? 8 : 4) * (size_t)c->q * c->N);
   const uint64_t gx = (c->nx + c->block - 1) / c->block;
   p.nblocks = gx * c->ny * c->nz;
+  if (has_adjoint2(c->d, c->sk)) {  // rows of the two-step kernel's tiles
+    const uint64_t n2 = (uint64_t)((c->nx + kA2X - 1) / kA2X) * ((c->ny + kA2Y - 1) / kA2Y);
+    if (n2 > p.nblocks) p.nblocks = n2;
+  }
   p.partial_bytes = align256(sizeof(double) * p.nblocks * c->q);
   p.total = p.state_bytes * (size_t)(p.nsnap + p.nsets * p.nsegslots + 3) + 2 * p.lam_bytes + p.partial_bytes;
   return p;
@@ -1088,6 +1102,8 @@ int lbmrv_adjoint(lbmrv_ctx* c, const void* f0, int ut_mode, double ut_alpha, co
   A.eq_maxwell = c->equilibrium == LBMRV_EQ_MAXWELLIAN ? 1u : 0u;
   A.stream = st;
   A.block = c->block;
+  const bool two_step = has_adjoint2(c->d, c->sk) && c->N <= kAdj2MaxNodes;
+  const void* lam_cur = cot_fN;
   // Reverse sweep, one segment of K steps at a time, last segment first (its
   // states are in place from the forward sweep).  Segment sg waits for its
   // recompute; once it is reversed its set is free, and segment sg - S is
@@ -1096,11 +1112,20 @@ int lbmrv_adjoint(lbmrv_ctx* c, const void* f0, int ut_mode, double ut_alpha, co
     if (recompute_any && sg < last && hipStreamWaitEvent(st, ev_rec(sg), 0) != hipSuccess) return LBMRV_ERR_HIP;
     const int64_t t0 = sg * K;
     const int64_t t1 = (t0 + K < nsteps) ? t0 + K : nsteps;
-    for (int64_t t = t1 - 1; t >= t0; --t) {
+    // two steps per launch where the lattice has that kernel, the last step
+    // of an odd count alone; the adjoint alternates between lam0 and lam1
+    // (never written by the launch that reads it), the first step reads the
+    // cotangent and the last one writes dJ/df0
+    for (int64_t t = t1 - 1; t >= t0;) {
+      const bool pair = two_step && t - 1 >= t0;
+      const int64_t tl = pair ? t - 1 : t;  // the launch's last step
       A.f = state(t);
-      A.lam_in = (t == nsteps - 1) ? cot_fN : ((t + 1) % 2 ? lam1 : lam0);
-      A.lam_out = (t == 0) ? grad_f0 : (t % 2 ? lam1 : lam0);
-      if ((e = E.adj[c->sk](A)) != hipSuccess) return LBMRV_ERR_HIP;
+      A.f_prev = pair ? state(t - 1) : nullptr;
+      A.lam_in = lam_cur;
+      A.lam_out = tl == 0 ? static_cast<void*>(grad_f0) : (lam_cur == lam0 ? lam1 : lam0);
+      if ((e = (pair ? E.adj2 : E.adj)[c->sk](A)) != hipSuccess) return LBMRV_ERR_HIP;
+      lam_cur = A.lam_out;
+      t = tl - 1;
     }
     if (recompute_any && sg - S >= 0) {
       if (hipEventRecord(ev_rev(sg), st) != hipSuccess || issue_recompute(sg - S) != hipSuccess)

@@ -193,8 +193,9 @@ hipError_t launch_convert_t(const void* in, void* out, double rho0, uint64_t N, 
 }
 
 struct AdjLaunch {
-  int mode;  // UT_ZERO or UT_FIELD
+  int mode;  // UT_ZERO, UT_FLUID or UT_FIELD
   const void* f;
+  const void* f_prev;  // two-step kernel only: f^{n-1} (f is f^n)
   const void* lam_in;
   void* lam_out;
   const float* ut;
@@ -230,6 +231,7 @@ hipError_t launch_adjoint_t(const AdjLaunch& L) {
   a.inv_lambda = T(L.inv_lambda);
   a.alpha = T(L.alpha);
   for (int k = 0; k < 27; ++k) a.s[k] = T(L.s[k]);
+  a.f_prev = L.f_prev;
   a.rnn = static_cast<const T*>(L.rnn);
   a.rnninv = static_cast<const T*>(L.rnninv);
   a.xcd_remap = L.xcd_remap;
@@ -253,6 +255,57 @@ hipError_t launch_adjoint_s(const AdjLaunch& L) {
   return L.rnn ? launch_adjoint_r<B, ST, 1>(L) : launch_adjoint_r<B, ST, 0>(L);
 }
 
+// Two reverse steps per launch (k_adjoint2): two-dimensional lattices with
+// FP32 arithmetic only; blocks of kA2X x kA2Y nodes.
+template <class B, int ST, int MODE, int RLX>
+hipError_t launch_adjoint2_t(const AdjLaunch& L) {
+  using T = typename Store<ST>::T;
+  AdjArgs<T> a{};
+  a.f = L.f;
+  a.f_prev = L.f_prev;
+  a.lam_in = static_cast<const T*>(L.lam_in);
+  a.lam_out = static_cast<T*>(L.lam_out);
+  a.ut = L.ut;
+  a.grad_ut = L.grad_ut;
+  a.partial = L.partial;
+  a.nx = L.nx;
+  a.ny = L.ny;
+  a.nz = L.nz;
+  a.N = L.N;
+  a.rho0 = T(L.rho0);
+  a.inv_lambda = T(L.inv_lambda);
+  a.alpha = T(L.alpha);
+  for (int k = 0; k < 27; ++k) a.s[k] = T(L.s[k]);
+  a.rnn = static_cast<const T*>(L.rnn);
+  a.rnninv = static_cast<const T*>(L.rnninv);
+  a.xcd_remap = L.xcd_remap;
+  a.eq_maxwell = L.eq_maxwell;
+  dim3 grid((L.nx + kA2X - 1) / kA2X, (L.ny + kA2Y - 1) / kA2Y, 1);
+  hipLaunchKernelGGL((k_adjoint2<B, ST, MODE, RLX>), grid, dim3(kA2X * kA2Y), 0, L.stream, a);
+  return hipGetLastError();
+}
+
+template <class B, int ST, int RLX>
+hipError_t launch_adjoint2_r(const AdjLaunch& L) {
+  if (L.mode == UT_ZERO) return launch_adjoint2_t<B, ST, UT_ZERO, RLX>(L);
+  if (L.mode == UT_FLUID) return launch_adjoint2_t<B, ST, UT_FLUID, RLX>(L);
+  if (L.mode == UT_FIELD) return launch_adjoint2_t<B, ST, UT_FIELD, RLX>(L);
+  return hipErrorInvalidValue;
+}
+
+template <class B, int ST>
+hipError_t launch_adjoint2_s(const AdjLaunch& L) {
+  if constexpr (B::Lat::D == 2 && ST != 0) {
+    return L.rnn ? launch_adjoint2_r<B, ST, 1>(L) : launch_adjoint2_r<B, ST, 0>(L);
+  } else {
+    (void)L;
+    return hipErrorInvalidValue;
+  }
+}
+
+// Whether a lattice and storage have the two-step reverse kernel.
+constexpr bool has_adjoint2(int d, int sk) { return d == 2 && sk != SK_F64; }
+
 // Per-(lattice, basis, storage) entry points, defined in the lattice translation
 // units (one unit per lattice and storage type, so they compile in parallel).
 #define LBMRV_DECLARE_LAUNCHERS(NAME, SKN)                                                  \
@@ -262,6 +315,7 @@ hipError_t launch_adjoint_s(const AdjLaunch& L) {
                                             hipStream_t st);                                \
   hipError_t launch_init_##NAME##_##SKN(const InitLaunch& L);                               \
   hipError_t launch_adjoint_##NAME##_##SKN(const AdjLaunch& L);                             \
+  hipError_t launch_adjoint2_##NAME##_##SKN(const AdjLaunch& L);                            \
   hipError_t launch_aa_finish_##NAME##_##SKN(void* f, uint32_t nx, uint32_t ny, uint32_t nz, uint64_t N, \
                                              const FinArgs& w, hipStream_t st);              \
   hipError_t launch_convert_##NAME##_##SKN(const void* in, void* out, double rho0, uint64_t N, \
@@ -282,6 +336,7 @@ hipError_t launch_adjoint_s(const AdjLaunch& L) {
   }                                                                                         \
   hipError_t launch_init_##NAME##_##SKN(const InitLaunch& L) { return launch_init_t<BASIS, ST>(L); } \
   hipError_t launch_adjoint_##NAME##_##SKN(const AdjLaunch& L) { return launch_adjoint_s<BASIS, ST>(L); } \
+  hipError_t launch_adjoint2_##NAME##_##SKN(const AdjLaunch& L) { return launch_adjoint2_s<BASIS, ST>(L); } \
   hipError_t launch_aa_finish_##NAME##_##SKN(void* f, uint32_t nx, uint32_t ny, uint32_t nz, uint64_t N, \
                                              const FinArgs& w, hipStream_t st) {             \
     return launch_aa_finish_t<BASIS, ST>(f, nx, ny, nz, N, w, st);                          \

@@ -55,11 +55,14 @@ def test_every_traffic_figure_is_the_one_its_profile_records():
         assert abs(got - gb) <= 6e-5, (workload, streaming, got, gb)
         # and the counters stay near the algorithmic bytes: within 1.1 %, or
         # 3.5 % where lines that two wavefronts share are fetched twice by
-        # choice: D3Q27's gathers stream every population past the caches, and
-        # at 512^3 a D3Q19 row spans two blocks that the natural order puts on
-        # different XCDs (both measured faster than the alternative)
+        # choice: D3Q27's pull gathers stream every population past the caches,
+        # and where a row spans several blocks that the natural order (arrays
+        # beyond the last-level cache) puts on different XCDs (D3Q19 at 512^3;
+        # D2Q9 at 4096^2 in the in-place form, whose scatter step runs 256-wide
+        # blocks); both choices measured faster than the alternative
         algo = float(rows[0][2])
-        limit = 0.035 if workload.startswith("d3q27") or workload == "d3q19_tgv512_f32_fluid" else 0.011
+        wide = workload in ("d3q19_tgv512_f32_fluid", "d2q9_shear4096_f32_fluid")
+        limit = 0.035 if workload.startswith("d3q27") or wide else 0.011
         assert abs(gb / algo - 1) < limit, (workload, streaming, gb, algo)
 
 

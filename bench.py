@@ -153,8 +153,12 @@ def cpu_baseline(name, budget_s=15.0):
 
     threads = min(16, os.cpu_count() or 1)
     steps, el = timed(lambda g, n: fast.run(lat, g, s, n, 1.0, smode, 1.0, field, threads=threads), f, budget_s)
-    # the same on one core, and Oracle A (NumPy) on the 64^2 D2Q9 shear wave
+    # the same on one core; the triangular-solve form of the same oracle (the
+    # one that wrote the stored full-size references) on all cores; and
+    # Oracle A (NumPy) on the 64^2 D2Q9 shear wave
     steps1, el1 = timed(lambda g, n: fast.run(lat, g, s, n, 1.0, smode, 1.0, field, threads=1), f, budget_s / 3)
+    steps_t, el_t = timed(lambda g, n: fast.run_tri(lat, g, s, n, 1.0, smode, 1.0, field, threads=threads), f,
+                          budget_s / 3)
     lat_a = lattices.make("d2q9_paper")
     rho_a, u_a = W.shear_wave(64, 0.01)
     steps_a, el_a = timed(lambda g, n: scheme.run(lat_a, g, W.RATES_D2Q9_GROUPED, n, mode=scheme.FLUID),
@@ -164,6 +168,7 @@ def cpu_baseline(name, budget_s=15.0):
                       "the same initial state, %d steps in %.1f s" % ("x".join(str(x) for x in reversed(sub)),
                                                                        steps, el),
             "one_core_value": round(nodes * steps1 / el1 / 1e6, 4),
+            "triangular_form_value": round(nodes * steps_t / el_t / 1e6, 4),
             "oracle_a_d2q9_64_mlups": round(64 * 64 * steps_a / el_a / 1e6, 4)}
 
 

@@ -698,6 +698,27 @@ __attribute__((amdgpu_waves_per_eu(step_min_waves<B, ST, KIND>()))) void k_step(
     const uint32_t zz = cz == 0 ? z : (cz > 0 ? zp : zm);
     return (zz * ny + yy) * nx + xx;
   };
+  // Destination node of direction j for the scatter forms.  For D3Q27 with
+  // FP16 storage the compiler otherwise forms all 27 destination offsets
+  // before the collision and keeps them live through it: 148 VGPRs, three
+  // wavefronts per SIMD, too few loads in flight for 2-byte populations.
+  // Node coordinates that an empty asm statement claims to rewrite after the
+  // collision keep that work behind it (96 VGPRs, five wavefronts; in-place
+  // odd step 187 -> 167 us at 192^3).  FP32 D3Q27 and D3Q19 ran 2-3 % slower
+  // at their higher occupancy this way, so they keep the early form.
+  constexpr bool late_dst = scatter_kind(KIND) && Q == 27 && ST == 2;
+  auto dst_node = [&](auto jj, uint32_t px, uint32_t py, uint32_t pz) -> uint32_t {
+    if constexpr (!late_dst) {
+      return nbr(jj, std::integral_constant<int, 1>{});
+    } else {
+      constexpr int J = jj;
+      constexpr int cx = L::c[J].x, cy = L::c[J].y, cz = L::c[J].z;
+      const uint32_t xx = cx == 0 ? px : (cx > 0 ? (px == nx - 1 ? 0 : px + 1) : (px == 0 ? nx - 1 : px - 1));
+      const uint32_t yy = cy == 0 ? py : (cy > 0 ? (py == ny - 1 ? 0 : py + 1) : (py == 0 ? ny - 1 : py - 1));
+      const uint32_t zz = cz == 0 ? pz : (cz > 0 ? (pz == nz - 1 ? 0 : pz + 1) : (pz == 0 ? nz - 1 : pz - 1));
+      return (zz * ny + yy) * nx + xx;
+    }
+  };
 
   const S* fin = static_cast<const S*>(a.fin);  // may alias fout for in-place collision
   S* fout = static_cast<S*>(a.fout);
@@ -756,6 +777,8 @@ __attribute__((amdgpu_waves_per_eu(step_min_waves<B, ST, KIND>()))) void k_step(
     }
     collide_node<B, T, MODE, RLX>(h, a, utf);
   }
+  uint32_t px = x, py = y, pz = z;
+  if constexpr (late_dst) asm volatile("" : "+v"(px), "+v"(py), "+v"(pz));
 
   // Stores: the gather forms write their own node (aligned, contiguous per
   // wavefront) and are streamed past the caches with non-temporal stores, which
@@ -778,7 +801,7 @@ __attribute__((amdgpu_waves_per_eu(step_min_waves<B, ST, KIND>()))) void k_step(
       }
     }
     if constexpr (KIND == K_PUSH || aa_odd) {
-      S* dst = &fout[(uint64_t)J * N + nbr(jj, std::integral_constant<int, 1>{})];
+      S* dst = &fout[(uint64_t)J * N + dst_node(jj, px, py, pz)];
       if constexpr (L::c[J].x == 0) __builtin_nontemporal_store(S(h[J]), dst);  // aligned with the wavefront
       else *dst = S(h[J]);
     } else {

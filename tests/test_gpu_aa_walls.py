@@ -26,7 +26,7 @@ def _need_gpu():
 
 
 @pytest.mark.parametrize("lattice,storage", [("d2q9", "f32"), ("d3q19", "f32"), ("d3q27", "f64"),
-                                             ("d3q19", "f16dev")])
+                                             ("d3q19", "f16dev"), ("d3q27", "f32"), ("d3q27", "f16dev")])
 @pytest.mark.parametrize("nsteps", [1, 4, 7])
 def test_in_place_form_matches_pull_bitwise(lattice, storage, nsteps):
     lat = oracle_lattice(lattice)
@@ -46,6 +46,32 @@ def test_in_place_form_matches_pull_bitwise(lattice, storage, nsteps):
     torch.cuda.synchronize()
     assert torch.equal(one, ref_out)
     assert torch.equal(b, ref_out)
+
+
+@pytest.mark.parametrize("mode", ["zero", "fluid", "field"])
+def test_d3q27_fp16_scatter_forms_match_pull_bitwise(mode):
+    """The scatter forms (push, in-place odd) of the D3Q27 FP16-deviation
+    step compute their destinations after the collision, the gather forms
+    before it; every form stores the same bits."""
+    lat = oracle_lattice("d3q27")
+    shape = (5, 6, 200)                                  # 192 + 8 along x
+    f0 = far_state(lat, shape, seed=13, amp=0.02, umax=0.08)
+    st, _ = to_storage(lat, f0, "f16dev")
+    fld = None
+    if mode == "field":
+        rng = np.random.default_rng(14)
+        fld = torch.from_numpy(rng.uniform(-0.1, 0.1, (3,) + shape).astype(np.float32)).cuda()
+    ctx = Lbmrv("d3q27", RATES[lat.q], tuple(reversed(shape)), "f16dev")
+    outs = {}
+    for streaming in ("pull", "push", "aa"):
+        ctx.set_streaming(streaming)
+        a = torch.from_numpy(st).cuda()
+        b = a if streaming == "aa" else torch.empty_like(a)
+        ctx.step(a, b, mode, 0.9, fld, 5)
+        outs[streaming] = b
+    torch.cuda.synchronize()
+    assert torch.equal(outs["push"], outs["pull"])
+    assert torch.equal(outs["aa"], outs["pull"])
 
 
 def _walls(lat):

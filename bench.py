@@ -38,12 +38,12 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_GB = {
     ("d2q9_shear2048_f32_fluid", "aa"): 0.3021,
     ("d2q9_shear4096_f32_fluid", "aa"): 1.2395,
-    ("d3q19_couette256_f32_fluid_walls", "aa"): 2.5504,
+    ("d3q19_couette256_f32_fluid_walls", "aa"): 2.5503,
     ("d3q19_tgv256_f16dev_fluid", "aa"): 1.2751,
-    ("d3q19_tgv256_f32_fluid", "aa"): 2.5504,
-    ("d3q19_tgv256_f32dev_fluid", "aa"): 2.5504,
+    ("d3q19_tgv256_f32_fluid", "aa"): 2.5503,
+    ("d3q19_tgv256_f32dev_fluid", "aa"): 2.5503,
     ("d3q19_tgv256_f64_fluid", "aa"): 5.1021,
-    ("d3q19_tgv512_f32_fluid", "aa"): 20.8276,
+    ("d3q19_tgv512_f32_fluid", "aa"): 20.8213,
     ("d3q27_tgv192_f16dev_field", "aa"): 0.8495,
     ("d3q27_tgv192_f32_field", "aa"): 1.6143,
     ("d2q9_shear2048_f32_fluid", "pull"): 0.3021,
@@ -55,7 +55,7 @@ TRAFFIC_GB = {
     ("d3q19_tgv256_f32_fluid_rawbasis", "pull"): 2.5512,
     ("d3q19_tgv256_f32dev_fluid", "pull"): 2.5508,
     ("d3q19_tgv256_f64_fluid", "pull"): 5.1006,
-    ("d3q19_tgv512_f32_fluid", "pull"): 21.081,
+    ("d3q19_tgv512_f32_fluid", "pull"): 21.0724,
     ("d3q27_tgv192_f16dev_field", "pull"): 0.8731,
     ("d3q27_tgv192_f32_field", "pull"): 1.6595,
 }

@@ -586,10 +586,10 @@ __device__ __forceinline__ void collide_node(T (&h)[B::Q], const StepArgs<T>& a,
 // ------------------------------------------------------------------ step kernel
 // Grid: (ceil(nx / blockDim.x), ceil(ny / blockDim.y), nz).  One thread = one
 // node (x, y, z).  The forms that store at the node (pull, collide,
-// transport, in-place even) run blocks of up to 1024 threads spanning several
-// consecutive rows (blockDim.y > 1), so that each block streams a few KB of
-// every population array contiguously (512 for FP64 storage, whose D3Q27
-// collision needs more than 128 registers).  The scatter forms (push,
+// transport, in-place even) may run blocks of up to 1024 threads spanning
+// several consecutive rows (blockDim.y > 1), so that each block streams a few
+// KB of every population array contiguously (512 for FP64 storage, whose D3Q27
+// collision needs more than 128 registers); the launcher picks the shape.  The scatter forms (push,
 // in-place odd) run one row of at most 256 threads, and their bound says so:
 // with the 1024-thread bound the D3Q27 in-place odd step was held to 128
 // registers and spilled to scratch.

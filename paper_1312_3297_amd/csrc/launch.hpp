@@ -45,6 +45,9 @@ struct MomLaunch {
   hipStream_t stream;
 };
 
+// LDS per compute unit on gfx950 (CDNA4)
+constexpr size_t kLdsPerCu = 160 * 1024;
+
 template <class B, int ST, int MODE, int KIND, int RLX>
 hipError_t launch_step_t(const StepLaunch& L) {
   using T = typename Store<ST>::T;
@@ -85,9 +88,24 @@ hipError_t launch_step_t(const StepLaunch& L) {
   // of two rows pack better (measured +2.6 % at 192^3 FP32; one row and three
   // to five rows were slower, and D3Q19 stays fastest at four rows)
   if (B::Q == 27 && by > 2u) by = 2u;
+  // D3Q19 with 4-byte populations, in-place even step (and the pull step on
+  // rows wider than one block): one 256-wide row per block and at most four
+  // blocks per CU, four wavefronts per SIMD as the odd step runs.  The cap is
+  // an LDS reservation the kernel never touches (kLdsPerCu / 4 per block).
+  // Same-GPU A/B: in place +1.1 % at 256^3 and +7.9 % at 512^3, pull +11 % at
+  // 512^3 (-0.4 % at 256^3, so 256-wide grids keep four-row blocks there);
+  // one-row blocks without the cap (seven per CU) lost 0.8 % at 256^3, and
+  // FP16, FP64, D3Q27 and D2Q9 gained nothing from either.
+  size_t lds_cap = 0;
+  if constexpr (B::Q == 19 && ST == 1 && (KIND == K_AA_EVEN || KIND == K_PULL)) {
+    if (KIND == K_AA_EVEN || L.nx > bx) {
+      by = 1u;
+      lds_cap = kLdsPerCu / 4;
+    }
+  }
   if (by > L.ny) by = L.ny;
   dim3 grid((L.nx + bx - 1) / bx, (L.ny + by - 1) / by, L.nz);
-  hipLaunchKernelGGL((k_step<B, ST, MODE, KIND, RLX>), grid, dim3(bx, by), 0, L.stream, a);
+  hipLaunchKernelGGL((k_step<B, ST, MODE, KIND, RLX>), grid, dim3(bx, by), lds_cap, L.stream, a);
   return hipGetLastError();
 }
 

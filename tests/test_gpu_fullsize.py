@@ -105,3 +105,33 @@ def test_d3q27_taylor_green_192_field(storage):
 def test_d2q9_double_shear_layer_f32_fluid(L):
     rho, u = workloads.double_shear_layer(L)
     _check("d2q9", (L, L), "f32", "fluid", "pull", workloads.RATES_D2Q9_SHEAR_LAYER, rho, u, 0.0, 7)
+
+
+# D3Q19 512^3 FP32 (Taylor-Green without noise; 2 x 10.2 GB of state in the
+# pull form): rows of 512 nodes span two blocks, and both timed forms run
+# one-row blocks, four per CU.  As in the benchmark, the GPU forms f^eq(rho, u)
+# itself (lbmrv_init_equilibrium, FP64 then rounded to FP32); the oracle forms
+# it on the host from the same rho and u over each sampled block, so a stored
+# value may differ by one FP32 rounding between the two starts.
+@pytest.mark.parametrize("streaming", ["pull", "aa"])
+def test_d3q19_taylor_green_512_f32_fluid(streaming):
+    lat = oracle_lattice("d3q19")
+    L = 512
+    shape = (L, L, L)
+    rho, u = workloads.taylor_green(L, 0.05)
+    ctx = Lbmrv("d3q19", workloads.RATES_D3Q19, shape, "f32")
+    ctx.set_streaming(streaming)
+    fin = ctx.init_equilibrium(torch.from_numpy(rho).to("cuda"), torch.from_numpy(u).to("cuda"), None, 0.0)
+    fout = fin if streaming == "aa" else torch.empty_like(fin)
+    ctx.step(fin, fout, "fluid", 1.0, None, NSTEPS)
+    pts = _samples(shape, np.random.default_rng(512))
+    idx = tuple(torch.tensor([p[a] for p in pts], device="cuda") for a in range(3))
+    gv = fout[(slice(None),) + idx].double().cpu().numpy()                  # (q, P)
+    del fin, fout
+    torch.cuda.synchronize()
+    R = NSTEPS
+    ref = []
+    for p in pts:
+        f0 = to_storage(lat, A.equilibrium(lat, _block(rho, p, R), _block(u, p, R)), "f32")[1]
+        ref.append(A.run(lat, f0, workloads.RATES_D3Q19, NSTEPS, mode=A.FLUID)[(slice(None),) + (R,) * 3])
+    assert rel(gv, np.stack(ref, axis=1)) <= 3e-7 * (NSTEPS + 4)

@@ -354,7 +354,13 @@ int lbmrv_lattice_tables(int lattice, int32_t *cdirs, double *w);
  *               nsteps, K) bytes, 256-byte aligned, owned by the caller
  * Either equilibrium (lbmrv_set_equilibrium) and a run-time basis are
  * differentiated; walls are not (UNSUPPORTED).
- * Asynchronous on hip_stream.  Errors: INVALID_ARG, UNSUPPORTED, ALIGNMENT, HIP.
+ * Asynchronous on hip_stream.  With more than one segment of K steps, the
+ * segments are recomputed on a second stream that the context creates at its
+ * first such call (default priority, on the device current then; a later
+ * call on another device returns INVALID_ARG) and orders against hip_stream
+ * with events: all of that work is complete before anything enqueued on
+ * hip_stream after the call runs.  Errors: INVALID_ARG, UNSUPPORTED,
+ * ALIGNMENT, HIP.
  */
 size_t lbmrv_adjoint_workspace_bytes(const lbmrv_ctx *c, int64_t nsteps, int64_t K);
 int lbmrv_adjoint(lbmrv_ctx *c, const void *f0, int ut_mode, double ut_alpha, const float *ut_field,

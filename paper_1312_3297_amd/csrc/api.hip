@@ -1006,16 +1006,25 @@ int lbmrv_adjoint(lbmrv_ctx* c, const void* f0, int ut_mode, double ut_alpha, co
     if (hipGetDevice(&dev) != hipSuccess) return LBMRV_ERR_HIP;
     if (c->astream && c->astream_dev != dev) return LBMRV_ERR_INVALID_ARG;  // bound to its first device
     if (!c->astream) {
-      if (hipStreamCreateWithFlags(&c->astream, hipStreamNonBlocking) != hipSuccess) {
+      // all or nothing: a failure leaves no stream or event behind, so the
+      // next call starts over
+      bool ok = hipStreamCreateWithFlags(&c->astream, hipStreamNonBlocking) == hipSuccess;
+      if (!ok) c->astream = nullptr;
+      for (auto& ev : c->aev)
+        if (ok && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+          ev = nullptr;
+          ok = false;
+        }
+      if (!ok) {
+        if (c->astream) (void)hipStreamDestroy(c->astream);
         c->astream = nullptr;
+        for (auto& ev : c->aev) {
+          if (ev) (void)hipEventDestroy(ev);
+          ev = nullptr;
+        }
         return LBMRV_ERR_HIP;
       }
       c->astream_dev = dev;
-      for (auto& ev : c->aev)
-        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
-          ev = nullptr;
-          return LBMRV_ERR_HIP;
-        }
     }
   }
   hipStream_t st2 = c->astream;

@@ -69,6 +69,20 @@ hipError_t launch_step_t(const StepLaunch& L) {
   a.xcd_remap = L.xcd_remap;
   for (int f = 0; f < 6; ++f)
     for (int ax = 0; ax < 3; ++ax) a.wall_coef[f][ax] = T(L.wall_coef[f][ax]);
+  // D3Q19 with FP16 storage, even in-place step, even nx: node pairs
+  // (k_aa_even_pair), up to 128 pairs of a row per block and as many rows as
+  // fill 256 threads
+  if constexpr (ST == 2 && KIND == K_AA_EVEN && B::Q == 19) {
+    if (L.nx % 2 == 0) {
+      const uint32_t npx = L.nx / 2;
+      const uint32_t bxp = npx >= 128u ? 128u : npx;
+      uint32_t byp = 256u / bxp;
+      if (byp > L.ny) byp = L.ny;
+      dim3 grid((npx + bxp - 1) / bxp, (L.ny + byp - 1) / byp, L.nz);
+      hipLaunchKernelGGL((k_aa_even_pair<B, MODE, RLX>), grid, dim3(bxp, byp), 0, L.stream, a);
+      return hipGetLastError();
+    }
+  }
   // block: whole wavefronts along x, and as many rows as fit in
   // step_max_threads threads.  The gather forms take rows up to that width
   // (1024-wide rows measured 1-2 % faster than 256 on 2048^2 and 4096^2 D2Q9

@@ -48,6 +48,30 @@ def test_in_place_form_matches_pull_bitwise(lattice, storage, nsteps):
     assert torch.equal(b, ref_out)
 
 
+@pytest.mark.parametrize("nx", [70, 71, 258])
+def test_d3q19_fp16_in_place_node_pairs_match_pull_bitwise(nx):
+    """With FP16 storage the D3Q19 even in-place step takes two nodes per
+    thread when nx is even (70: 35 pairs a row, several rows per block; 258:
+    129 pairs, two blocks a row) and one otherwise (71); every form stores the
+    bits of the pull form, in both block orders."""
+    lat = oracle_lattice("d3q19")
+    shape = (4, 5, nx)
+    f0 = far_state(lat, shape, seed=16, amp=0.02, umax=0.08)
+    st, _ = to_storage(lat, f0, "f16dev")
+    ctx = Lbmrv("d3q19", RATES[19], tuple(reversed(shape)), "f16dev")
+    ctx.set_streaming("pull")
+    ref_in = torch.from_numpy(st).cuda()
+    ref = torch.empty_like(ref_in)
+    ctx.step(ref_in, ref, "fluid", 1.0, None, 6)
+    ctx.set_streaming("aa")
+    for order in ("natural", "xcd"):
+        ctx.set_block_order(order)
+        one = torch.from_numpy(st).cuda()
+        ctx.step(one, one, "fluid", 1.0, None, 6)
+        torch.cuda.synchronize()
+        assert torch.equal(one, ref), order
+
+
 @pytest.mark.parametrize("mode", ["zero", "fluid", "field"])
 def test_d3q27_fp16_scatter_forms_match_pull_bitwise(mode):
     """The scatter forms (push, in-place odd) of the D3Q27 FP16-deviation
@@ -159,6 +183,11 @@ def test_in_place_form_with_walls_matches_pull_bitwise(lattice, storage, nsteps)
 
 
 def test_in_place_form_with_walls_fp16_within_tolerance():
+    """FP16 deviations with a moving wall: the in-place odd step stores a
+    bounced population with the wall's momentum already added (one FP16
+    rounding of the sum), the pull form stores it before the bounce and adds
+    the momentum in FP32 when it reads it, so the two forms agree to the FP16
+    tolerance rather than bit for bit; both are held to the oracle."""
     lat = oracle_lattice("d3q19")
     shape = (6, 7, 70)
     f0 = far_state(lat, shape, seed=15, amp=0.02, umax=0.05)

@@ -39,7 +39,7 @@ TRAFFIC_GB = {
     ("d2q9_shear2048_f32_fluid", "aa"): 0.3021,
     ("d2q9_shear4096_f32_fluid", "aa"): 1.2395,
     ("d3q19_couette256_f32_fluid_walls", "aa"): 2.5503,
-    ("d3q19_tgv256_f16dev_fluid", "aa"): 1.2751,
+    ("d3q19_tgv256_f16dev_fluid", "aa"): 1.2752,
     ("d3q19_tgv256_f32_fluid", "aa"): 2.5503,
     ("d3q19_tgv256_f32dev_fluid", "aa"): 2.5503,
     ("d3q19_tgv256_f64_fluid", "aa"): 5.1021,

@@ -42,6 +42,9 @@ def test_every_traffic_figure_is_the_one_its_profile_records():
         text = _profile_for(workload, streaming)
         rows = re.findall(r"^\| `k_step<[^`]*, (\d), \d>`[^|]*\| [\d,.]+ \| [\d,.]+ \| ([\d.]+) \| ([\d.]+) \|$",
                           text, re.M)
+        # the D3Q19 FP16 even in-place step runs on node pairs (kind 4)
+        rows += [("4",) + r for r in re.findall(
+            r"^\| `k_aa_even_pair<[^`]*>`[^|]*\| [\d,.]+ \| [\d,.]+ \| ([\d.]+) \| ([\d.]+) \|$", text, re.M)]
         assert rows, (workload, streaming)
         if streaming == "aa":
             vals = [float(t) for kind, t, _ in rows if kind in "456"]

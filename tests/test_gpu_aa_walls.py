@@ -48,12 +48,13 @@ def test_in_place_form_matches_pull_bitwise(lattice, storage, nsteps):
     assert torch.equal(b, ref_out)
 
 
-@pytest.mark.parametrize("nx", [70, 71, 258])
+@pytest.mark.parametrize("nx", [2, 4, 70, 71, 258])
 def test_d3q19_fp16_in_place_node_pairs_match_pull_bitwise(nx):
     """With FP16 storage the D3Q19 even in-place step takes two nodes per
-    thread when nx is even (70: 35 pairs a row, several rows per block; 258:
-    129 pairs, two blocks a row) and one otherwise (71); every form stores the
-    bits of the pull form, in both block orders."""
+    thread when nx is even (2 and 4: one and two pairs a row, the odd step's
+    periodic wrap next to every pair; 70: 35 pairs a row, several rows per
+    block; 258: 129 pairs, two blocks a row) and one otherwise (71); every form
+    stores the bits of the pull form, in both block orders."""
     lat = oracle_lattice("d3q19")
     shape = (4, 5, nx)
     f0 = far_state(lat, shape, seed=16, amp=0.02, umax=0.08)

@@ -40,10 +40,10 @@ TRAFFIC_GB = {
     ("d2q9_shear4096_f32_fluid", "aa"): 1.2395,
     ("d3q19_couette256_f32_fluid_walls", "aa"): 2.5503,
     ("d3q19_tgv256_f16dev_fluid", "aa"): 1.2752,
-    ("d3q19_tgv256_f32_fluid", "aa"): 2.5503,
-    ("d3q19_tgv256_f32dev_fluid", "aa"): 2.5503,
+    ("d3q19_tgv256_f32_fluid", "aa"): 2.5502,
+    ("d3q19_tgv256_f32dev_fluid", "aa"): 2.5502,
     ("d3q19_tgv256_f64_fluid", "aa"): 5.1021,
-    ("d3q19_tgv512_f32_fluid", "aa"): 20.8213,
+    ("d3q19_tgv512_f32_fluid", "aa"): 20.8212,
     ("d3q27_tgv192_f16dev_field", "aa"): 0.8495,
     ("d3q27_tgv192_f32_field", "aa"): 1.6143,
     ("d2q9_shear2048_f32_fluid", "pull"): 0.3021,

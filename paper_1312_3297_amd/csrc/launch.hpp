@@ -45,8 +45,15 @@ struct MomLaunch {
   hipStream_t stream;
 };
 
-// LDS per compute unit on gfx950 (CDNA4)
+// LDS per compute unit on gfx950 (CDNA4), and per-block reservations that let
+// at most n blocks share a CU: a multiple of 4 KB between kLdsPerCu / (n + 1)
+// and kLdsPerCu / n with room on both sides (53 KB, for three blocks, was
+// measured to admit only two: the allocation is coarser than 1 KB)
 constexpr size_t kLdsPerCu = 160 * 1024;
+constexpr size_t lds_for_blocks(size_t n) {
+  return ((kLdsPerCu / n + kLdsPerCu / (n + 1)) / 2) / 4096 * 4096;
+}
+static_assert(lds_for_blocks(4) == 36 * 1024 && lds_for_blocks(3) == 44 * 1024, "LDS reservations");
 
 template <class B, int ST, int MODE, int KIND, int RLX>
 hipError_t launch_step_t(const StepLaunch& L) {
@@ -105,17 +112,24 @@ hipError_t launch_step_t(const StepLaunch& L) {
   // D3Q19 with 4-byte populations, in-place even step (and the pull step on
   // rows wider than one block): one 256-wide row per block and at most four
   // blocks per CU, four wavefronts per SIMD as the odd step runs.  The cap is
-  // an LDS reservation the kernel never touches (kLdsPerCu / 4 per block).
+  // an LDS reservation the kernel never touches (lds_for_blocks).
   // Same-GPU A/B: in place +1.1 % at 256^3 and +7.9 % at 512^3, pull +11 % at
   // 512^3 (-0.4 % at 256^3, so 256-wide grids keep four-row blocks there);
   // one-row blocks without the cap (seven per CU) lost 0.8 % at 256^3, and
-  // FP16, FP64, D3Q27 and D2Q9 gained nothing from either.
+  // FP16, FP64, D3Q27 and D2Q9 gained nothing from either.  The odd step
+  // (four wavefronts per SIMD by its registers) runs at most three blocks per
+  // CU where a row fits one block: in place +1.2 to +1.4 % at 256^3, odd step
+  // 420 -> 406-410 us (two blocks: -2 %; three at 512^3, rows of two blocks:
+  // -1.8 %).
   size_t lds_cap = 0;
   if constexpr (B::Q == 19 && ST == 1 && (KIND == K_AA_EVEN || KIND == K_PULL)) {
     if (KIND == K_AA_EVEN || L.nx > bx) {
       by = 1u;
-      lds_cap = kLdsPerCu / 4;
+      lds_cap = lds_for_blocks(4);
     }
+  }
+  if constexpr (B::Q == 19 && ST == 1 && KIND == K_AA_ODD) {
+    if (L.nx <= bx) lds_cap = lds_for_blocks(3);
   }
   if (by > L.ny) by = L.ny;
   dim3 grid((L.nx + bx - 1) / bx, (L.ny + by - 1) / by, L.nz);

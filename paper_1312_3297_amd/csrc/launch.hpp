@@ -76,11 +76,12 @@ hipError_t launch_step_t(const StepLaunch& L) {
   a.xcd_remap = L.xcd_remap;
   for (int f = 0; f < 6; ++f)
     for (int ax = 0; ax < 3; ++ax) a.wall_coef[f][ax] = T(L.wall_coef[f][ax]);
-  // D3Q19 with FP16 storage, even in-place step, even nx: node pairs
-  // (k_aa_even_pair), up to 128 pairs of a row per block and as many rows as
-  // fill 256 threads
+  // D3Q19 with FP16 storage, even in-place step: node pairs (k_aa_even_pair),
+  // up to 128 pairs of a row per block and as many rows as fill 256 threads
   if constexpr (ST == 2 && KIND == K_AA_EVEN && B::Q == 19) {
-    if (L.nx % 2 == 0) {
+    // whole words: nx even (so N is even and every slot starts on a word) and
+    // the arrays 4-byte aligned (the interface asks for 2)
+    if (L.nx % 2 == 0 && reinterpret_cast<uintptr_t>(L.fin) % 4 == 0 && reinterpret_cast<uintptr_t>(L.fout) % 4 == 0) {
       const uint32_t npx = L.nx / 2;
       const uint32_t bxp = npx >= 128u ? 128u : npx;
       uint32_t byp = 256u / bxp;

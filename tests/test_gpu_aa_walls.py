@@ -73,6 +73,29 @@ def test_d3q19_fp16_in_place_node_pairs_match_pull_bitwise(nx):
         assert torch.equal(one, ref), order
 
 
+def test_d3q19_fp16_in_place_on_an_array_with_2_byte_alignment():
+    """The interface asks FP16 arrays for 2-byte alignment only; an array that
+    starts 2 bytes past a word boundary runs the even step one node per
+    thread and still stores the pull form's bits."""
+    lat = oracle_lattice("d3q19")
+    shape = (4, 5, 70)
+    f0 = far_state(lat, shape, seed=17, amp=0.02, umax=0.08)
+    st, _ = to_storage(lat, f0, "f16dev")
+    ctx = Lbmrv("d3q19", RATES[19], tuple(reversed(shape)), "f16dev")
+    ctx.set_streaming("pull")
+    ref_in = torch.from_numpy(st).cuda()
+    ref = torch.empty_like(ref_in)
+    ctx.step(ref_in, ref, "fluid", 1.0, None, 6)
+    ctx.set_streaming("aa")
+    flat = torch.zeros(st.size + 1, dtype=ref.dtype, device="cuda")
+    one = flat[1:].view(st.shape)
+    assert one.data_ptr() % 4 == 2
+    one.copy_(torch.from_numpy(st).cuda())
+    ctx.step(one, one, "fluid", 1.0, None, 6)
+    torch.cuda.synchronize()
+    assert torch.equal(one, ref)
+
+
 @pytest.mark.parametrize("mode", ["zero", "fluid", "field"])
 def test_d3q27_fp16_scatter_forms_match_pull_bitwise(mode):
     """The scatter forms (push, in-place odd) of the D3Q27 FP16-deviation

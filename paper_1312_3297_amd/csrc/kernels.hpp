@@ -604,8 +604,10 @@ constexpr int step_max_threads() {
 // The D3Q27 step with FP16 storage at the node takes 97 VGPRs, one past the 96
 // that let a SIMD hold 5 of its wavefronts: at 5 it spends ~9 % more
 // instructions on moves but measured 3.5 % faster (6 would spill to scratch).
-// The scatter forms need more registers for their destinations and are left
-// unconstrained (at 5 the in-place odd step spilled 216 bytes per lane).
+// The scatter forms are left unconstrained: with their destinations formed
+// after the collision (late_dst below) the D3Q27 FP16 ones hold 93-96 VGPRs
+// and five wavefronts anyway; before that change a request for 5 made the
+// in-place odd step spill 216 bytes per lane.
 template <class B, int ST, int KIND>
 constexpr int step_min_waves() {
   return (B::Q == 27 && ST == 2 && !scatter_kind(KIND)) ? 5 : 1;

@@ -42,6 +42,7 @@ TRAFFIC_GB = {
     ("d3q19_tgv256_f16dev_fluid", "aa"): 1.2752,
     ("d3q19_tgv256_f32_fluid", "aa"): 2.5502,
     ("d3q19_tgv256_f32dev_fluid", "aa"): 2.5502,
+    ("d3q19_tgv256_slab32_f32dev_fluid", "aa"): 0.3189,
     ("d3q19_tgv256_f64_fluid", "aa"): 5.1021,
     ("d3q19_tgv512_f32_fluid", "aa"): 20.8212,
     ("d3q27_tgv192_f16dev_field", "aa"): 0.8495,
@@ -72,6 +73,10 @@ WORKLOADS = {
     "d3q19_couette256_f32_fluid_walls": ("d3q19", (256, 256, 256), "f32", "fluid"),
     "d3q19_tgv256_f64_fluid": ("d3q19", (256, 256, 256), "f64", "fluid"),
     "d3q19_tgv256_f32dev_fluid": ("d3q19", (256, 256, 256), "f32dev", "fluid"),
+    # one GPU's share of the headline case split into eight z-slabs: the first
+    # 32 planes of the same Taylor-Green state (periodic in z here; a sharded
+    # run would exchange the face populations instead)
+    "d3q19_tgv256_slab32_f32dev_fluid": ("d3q19", (256, 256, 32), "f32dev", "fluid"),
     # the headline case at 512^3 (2 x 10.2 GB of state), to show the rate holds
     # for a state 8x larger; no seeded noise (it would be 20 GB on the host)
     "d3q19_tgv512_f32_fluid": ("d3q19", (512, 512, 512), "f32", "fluid"),
@@ -89,7 +94,7 @@ def build_state(name, ctx, torch):
     from paper_1312_3297_amd import workloads as W
     lattice, dims, storage, mode = WORKLOADS[name]
     if lattice == "d3q19":
-        rho, u = W.taylor_green(dims[0], 0.05)
+        rho, u = W.taylor_green(dims[0], 0.05, shape=tuple(reversed(dims)))
         noise, amp, seed = dims[0] <= 256, 1e-5, 1313
     elif lattice == "d3q27":
         rho, u = W.taylor_green(dims[0], 0.05)

@@ -94,6 +94,13 @@ def test_d3q19_taylor_green_256_other_storages_fluid(storage):
     _check("d3q19", (256, 256, 256), storage, "fluid", "pull", workloads.RATES_D3Q19, rho, u, 1e-5, 1313)
 
 
+def test_d3q19_taylor_green_slab_f32dev_fluid():
+    """One GPU's share of the headline case in eight z-slabs (256 x 256 x 32),
+    in place, in the launch shape the benchmark times."""
+    rho, u = workloads.taylor_green(256, 0.05, shape=(32, 256, 256))
+    _check("d3q19", (32, 256, 256), "f32dev", "fluid", "aa", workloads.RATES_D3Q19, rho, u, 1e-5, 1313)
+
+
 @pytest.mark.parametrize("storage", ["f32", "f16dev"])
 def test_d3q27_taylor_green_192_field(storage):
     rho, u = workloads.taylor_green(192, 0.05)

@@ -49,7 +49,9 @@
  *
  * Memory and streams.  All arrays passed to lbmrv_step / lbmrv_moments /
  * lbmrv_conservation are device pointers owned by the caller, aligned to their
- * element size, on the device that is current when the call is made.  A
+ * element size, on the device that is current when the call is made (an
+ * LBMRV_F16DEV D3Q19 state that is also 4-byte aligned, with an even nx, takes
+ * a faster path in the in-place form; results are the same bits).  A
  * `hip_stream` argument is a hipStream_t (NULL = the null stream); work is
  * enqueued on it asynchronously unless stated otherwise.  The context owns only
  * its parameters, (after the first lbmrv_conservation call) a small device

@@ -48,15 +48,17 @@ def test_in_place_form_matches_pull_bitwise(lattice, storage, nsteps):
     assert torch.equal(b, ref_out)
 
 
-@pytest.mark.parametrize("nx", [2, 4, 70, 71, 258])
+@pytest.mark.parametrize("nx", [2, 4, 70, 71, 128, 256, 258, 384])
 def test_d3q19_fp16_in_place_node_pairs_match_pull_bitwise(nx):
     """With FP16 storage the D3Q19 even in-place step takes two nodes per
     thread when nx is even (2 and 4: one and two pairs a row, the odd step's
     periodic wrap next to every pair; 70: 35 pairs a row, several rows per
-    block; 258: 129 pairs, two blocks a row) and one otherwise (71); every form
-    stores the bits of the pull form, in both block orders."""
+    block; 128, 256, 384: one, two and three wavefronts a row; 258: 129 pairs,
+    two blocks a row) and one otherwise (71); five rows leave the last block
+    of each plane partly empty.  Every form stores the bits of the pull form,
+    in both block orders."""
     lat = oracle_lattice("d3q19")
-    shape = (4, 5, nx)
+    shape = (3, 5, nx)
     f0 = far_state(lat, shape, seed=16, amp=0.02, umax=0.08)
     st, _ = to_storage(lat, f0, "f16dev")
     ctx = Lbmrv("d3q19", RATES[19], tuple(reversed(shape)), "f16dev")

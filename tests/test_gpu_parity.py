@@ -334,6 +334,31 @@ def test_fp16_subnormal_deviations(lattice, mode):
     assert np.abs(got.astype(np.float64) - ref_dev).max() <= 2.0 ** -25 * 1.01
 
 
+def test_fp16_subnormal_deviations_in_place_node_pairs():
+    """The same subnormal rest state on D3Q19 with an even nx, in place: the
+    even step runs on node pairs (two 2-byte halves per word), and after two
+    and three steps the state still holds nonzero subnormals and equals the
+    pull form's bits."""
+    lat = oracle_lattice("d3q19")
+    shape = (3, 4, 6)
+    rng = np.random.default_rng(11)
+    w = lat.w.reshape((-1,) + (1,) * lat.d)
+    f0 = w * np.ones((lat.q,) + shape) + 1e-6 * rng.uniform(-1, 1, (lat.q,) + shape)
+    ctx = Lbmrv("d3q19", ctx_rates(lat), tuple(reversed(shape)), "f16dev")
+    for nsteps in (2, 3):
+        ctx.set_streaming("pull")
+        a = ctx.import_f64(gpu(f0))
+        ref = torch.empty_like(a)
+        ctx.step(a, ref, "fluid", 1.0, None, nsteps)
+        ctx.set_streaming("aa")
+        one = ctx.import_f64(gpu(f0))
+        ctx.step(one, one, "fluid", 1.0, None, nsteps)
+        torch.cuda.synchronize()
+        got = one.cpu().numpy().astype(np.float64)
+        assert np.abs(got).max() < 2.0 ** -14 and np.count_nonzero(got) > 0.8 * got.size
+        assert torch.equal(one, ref), nsteps
+
+
 def ctx_rates(lat):
     return {9: workloads.RATES_D2Q9_GROUPED, 19: workloads.RATES_D3Q19, 27: workloads.RATES_D3Q27}[lat.q]
 
